@@ -1,0 +1,171 @@
+"""CPU FP64 oracle for the NPF hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this
+package.  It wraps ``npf_oracle.c`` (plain C, double precision) with ctypes and shares
+no code with the HIP library; the two meet only in the seeded inputs of
+``paper_2509_08968_amd.inputs``.
+
+Functions follow the paper (arXiv 2509.08968):
+  full()      Alg. 2 literally, on full tensors (small n only);
+  sym()       the same quantities from packed symmetric storage, per output mode;
+  assemble()  Alg. 2 step 20 / eq. (7): NPF[k, i] = Phi[k, i] (delta Psi[i, k] + sum_M P_M[i, k]);
+  npf()       orders 2..N of one system, summed and assembled.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "npf_oracle.c")
+_LIB = os.path.join(_HERE, "libnpf_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CFLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+          "-Wall", "-Wextra", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/libnpf_oracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=True)
+            L = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+            L.npfo_full.argtypes = [i64, i32, P, P, P, P, dbl, dbl, P, P, P]
+            L.npfo_sym.argtypes = [i64, i32, P, P, P, P, dbl, dbl, P, i64, P, P, P, i32]
+            L.npfo_assemble.argtypes = [i64, P, P, dbl, P, P]
+            L.npfo_binom.argtypes = [i64, i64]
+            L.npfo_binom.restype = i64
+            for f in (L.npfo_full, L.npfo_sym, L.npfo_assemble):
+                f.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+class use_library:
+    """Context manager that points this module at another build of the oracle source
+    (the mutation tests compile deliberately broken copies and check that a pin fails)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        with _lock:
+            self.saved = _lib
+            _lib = None
+        L = ctypes.CDLL(self.path)
+        global _LIB
+        self.saved_path, _LIB = _LIB, self.path
+        lib()
+        _LIB = self.saved_path
+        return L
+
+    def __exit__(self, *exc):
+        global _lib
+        with _lock:
+            _lib = self.saved
+        return False
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def unpack_full(A_packed: np.ndarray, n: int, M: int) -> np.ndarray:
+    """Expand packed symmetric storage to the full [n, n^M] tensor (every ordering of a
+    sorted tuple gets the stored value)."""
+    full = np.zeros((n,) + (n,) * M)
+    for t in itertools.product(range(n), repeat=M):
+        s = sorted(t)
+        r = sum(int(np.round(_binom(x + i, i + 1))) for i, x in enumerate(s))
+        full[(slice(None),) + t] = A_packed[:, r]
+    return full.reshape(n, n ** M)
+
+
+def _binom(a, b):
+    from math import comb
+    return comb(a, b) if 0 <= b <= a else 0
+
+
+def full(sys, M: int, A_full: np.ndarray = None):
+    """Alg. 2 on full tensors.  Returns dict C, h [n, n^M] and P [n, n]."""
+    n = sys.n
+    if A_full is None:
+        A_full = unpack_full(sys.A[M], n, M)
+    A_full = np.ascontiguousarray(A_full, dtype=np.float64)
+    C = np.empty((n, n ** M), np.complex128)
+    h = np.empty_like(C)
+    P = np.empty((n, n), np.complex128)
+    lam, V, U = _c128(sys.lam), _c128(sys.V), _c128(sys.U)
+    rc = lib().npfo_full(n, M, _p(lam), _p(V), _p(U), _p(A_full), sys.eps, sys.delta,
+                         _p(C), _p(h), _p(P))
+    if rc != 0:
+        raise ValueError("npfo_full rejected its arguments")
+    return {"C": C, "h": h, "P": P}
+
+
+def sym(sys, M: int, modes=None, want_C: bool = False, want_h: bool = False,
+        nthreads: int = 0, A_packed: np.ndarray = None):
+    """Packed-symmetric evaluation.  Returns dict with P [len(modes), n] and optionally
+    C, h [len(modes), binom(n+M-1, M)] over colex-ranked sorted tuples."""
+    n = sys.n
+    A = np.ascontiguousarray(sys.A[M] if A_packed is None else A_packed, dtype=np.float64)
+    modes = np.arange(n, dtype=np.int64) if modes is None else np.asarray(modes, np.int64)
+    U_M = _binom(n + M - 1, M)
+    C = np.empty((len(modes), U_M), np.complex128) if want_C else None
+    h = np.empty((len(modes), U_M), np.complex128) if want_h else None
+    P = np.empty((len(modes), n), np.complex128)
+    lam, V, U = _c128(sys.lam), _c128(sys.V), _c128(sys.U)
+    rc = lib().npfo_sym(n, M, _p(lam), _p(V), _p(U), _p(A), sys.eps, sys.delta,
+                        _p(modes), len(modes), _p(C), _p(h), _p(P), int(nthreads))
+    if rc != 0:
+        raise ValueError("npfo_sym rejected its arguments")
+    out = {"P": P, "modes": modes}
+    if want_C:
+        out["C"] = C
+    if want_h:
+        out["h"] = h
+    return out
+
+
+def assemble(sys, Psum=None):
+    """Alg. 2 step 20: NPF [n states, n modes]."""
+    n = sys.n
+    out = np.empty((n, n), np.complex128)
+    Ps = None if Psum is None else _c128(Psum)
+    rc = lib().npfo_assemble(n, _p(_c128(sys.V)), _p(_c128(sys.U)), sys.delta, _p(Ps), _p(out))
+    if rc != 0:
+        raise ValueError("npfo_assemble rejected its arguments")
+    return out
+
+
+def npf(sys, method: str = "sym", nthreads: int = 0):
+    """All orders 2..N of one system: returns (NPF, {M: P_M})."""
+    Ps = {}
+    for M in sys.orders:
+        Ps[M] = full(sys, M)["P"] if method == "full" else sym(sys, M, nthreads=nthreads)["P"]
+    Psum = sum(Ps.values()) if Ps else None
+    return assemble(sys, Psum), Ps

@@ -1,0 +1,300 @@
+"""Pins of the CPU oracle to the paper and to mathematics (no GPU).
+
+Each test fixes the oracle against something other than itself:
+  P1  Psi A1 Phi = diag(lambda)                       (inputs; eq. (1)-(3) setting)
+  P2  A_M = 0 gives the linear PF Phi o Psi^T, rows summing to delta; P_M ~ delta^M (eq. (7))
+  P3  C symmetric in its lower indices; conjugate modes give conjugate C and NPF
+  P4  invariance under eigenvector scaling, covariance under mode permutation
+  P5  diagonal system closed form (hand-derived from eq. (4), (7))
+  P6  damped oscillator with a quadratic term, closed form (eq. (4), (7))
+  P7  C from exact polarization finite differences of the polynomial vector field
+  P8  homological residual: with y = z + h(z) the z-dynamics is Lambda z + O(|z|^(2M-1))
+  P10 full-tensor Alg. 2 equals the packed-symmetric evaluation
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_08968_amd import inputs as I
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def full_to_sorted(X, n, M):
+    tups = I.sorted_tuples(n, M)
+    idx = [np.ravel_multi_index(tuple(t), (n,) * M) for t in tups]
+    return X[:, idx]
+
+
+def small(n, M, seed, **kw):
+    return I.dense_system(n, [M], seed, **kw)
+
+
+# ------------------------------------------------------------------ packing
+def test_colex_rank_is_bijection():
+    for n, m in [(1, 3), (5, 1), (6, 2), (5, 3), (4, 4), (7, 3)]:
+        tups = I.sorted_tuples(n, m)
+        assert len(tups) == I.n_sorted(n, m) == math.comb(n + m - 1, m)
+        assert [I.colex_rank(t) for t in tups] == list(range(len(tups)))
+
+
+# ------------------------------------------------------------------ P1
+def test_p1_jacobian_diagonalised():
+    s = I.workload_small()
+    D = s.U @ s.A1 @ s.V
+    assert np.abs(D - np.diag(s.lam)).max() < 1e-12 * np.abs(s.lam).max()
+    assert np.abs(s.U @ s.V - np.eye(s.n)).max() < 1e-12
+
+
+# ------------------------------------------------------------------ P2
+@pytest.mark.parametrize("delta", [1.0, 0.3])
+def test_p2_linear_limit(delta):
+    s = small(6, 2, 7, delta=delta)
+    s.A[2] = np.zeros_like(s.A[2])
+    npf, Ps = oracle.npf(s)
+    assert np.abs(Ps[2]).max() == 0.0
+    lin = delta * s.V * s.U.T
+    assert rel(npf, lin) < 1e-15
+    assert np.abs(npf.sum(axis=1) - delta).max() < 1e-12
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_p2_order_scales_as_delta_power(M):
+    s = small(5, M, 11 + M)
+    P1 = oracle.sym(s, M)["P"]
+    s.delta = 0.5
+    Ph = oracle.sym(s, M)["P"]
+    assert rel(Ph, P1 * 0.5 ** M) < 1e-13
+
+
+# ------------------------------------------------------------------ P3
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_p3_lower_index_symmetry_of_full_tensor_path(M):
+    n = 4
+    s = small(n, M, 21 + M)
+    C = oracle.full(s, M)["C"].reshape((n,) * (M + 1))
+    for perm in itertools.permutations(range(M)):
+        Cp = np.transpose(C, (0,) + tuple(1 + p for p in perm))
+        assert np.abs(Cp - C).max() <= 1e-14 * np.abs(C).max()
+
+
+@pytest.mark.parametrize("M", [2, 3])
+def test_p3_conjugate_modes(M):
+    n = 6
+    s = small(n, M, 31 + M)
+    out = oracle.sym(s, M, want_C=True)
+    C = out["C"]
+    conj = np.arange(n) ^ 1           # modes 2m and 2m+1 are a conjugate pair
+    tups = I.sorted_tuples(n, M)
+    ctup = np.sort(conj[tups], axis=1)
+    cr = np.array([I.colex_rank(t) for t in ctup])
+    assert rel(C[conj][:, cr], np.conj(C)) < 1e-13
+    npf, _ = oracle.npf(s)
+    assert rel(npf[:, conj], np.conj(npf)) < 1e-13
+
+
+# ------------------------------------------------------------------ P4
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_p4_eigenvector_scaling_and_mode_permutation(M):
+    n = 5
+    s = small(n, M, 41 + M)
+    base, _ = oracle.npf(s)
+    rng = np.random.default_rng(5)
+    c = rng.uniform(0.3, 3.0, n) * np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    s2 = small(n, M, 41 + M)
+    s2.V = s.V * c[None, :]
+    s2.U = s.U / c[:, None]
+    scaled, _ = oracle.npf(s2)
+    assert rel(scaled, base) < 1e-12
+    perm = rng.permutation(n)
+    s3 = small(n, M, 41 + M)
+    s3.lam, s3.V, s3.U = s.lam[perm], s.V[:, perm], s.U[perm, :]
+    permuted, _ = oracle.npf(s3)
+    assert rel(permuted, base[:, perm]) < 1e-13
+
+
+# ------------------------------------------------------------------ P5
+def test_p5_diagonal_closed_form():
+    n = 3
+    rng = np.random.default_rng(3)
+    lam = np.array([-0.3 + 1.1j, -0.7 - 0.4j, -1.2 + 0.0j])
+    A2 = rng.standard_normal((n, I.n_sorted(n, 2)))
+    delta = 0.7
+    s = I.System("diag", n, lam, np.eye(n, dtype=complex), np.eye(n, dtype=complex),
+                 np.real(np.diag(lam)), {2: A2}, {2: None}, delta=delta)
+    out = oracle.sym(s, 2, want_C=True)
+    tups = I.sorted_tuples(n, 2)
+    assert rel(out["C"], A2 / 2.0) < 1e-15
+    r_kk = [I.colex_rank((k, k)) for k in range(n)]
+    P_exp = np.zeros((n, n), complex)
+    for j in range(n):
+        for k in range(n):
+            P_exp[j, k] = -delta ** 2 * A2[j, r_kk[k]] / (2.0 * (2 * lam[k] - lam[j]))
+    assert rel(out["P"], P_exp) < 1e-14
+    npf, _ = oracle.npf(s)
+    exp = np.diag([delta - delta ** 2 * A2[k, r_kk[k]] / (2 * lam[k]) for k in range(n)])
+    assert rel(npf, exp) < 1e-14
+    assert len(tups) == I.n_sorted(n, 2)
+
+
+# ------------------------------------------------------------------ P6
+@pytest.mark.parametrize("method", ["full", "sym"])
+def test_p6_damped_oscillator_closed_form(method):
+    w, z, kappa, delta = 2.0, 0.15, 0.8, 0.6
+    l1 = complex(-z * w, w * math.sqrt(1 - z * z))
+    l2 = l1.conjugate()
+    lam = np.array([l1, l2])
+    Phi = np.array([[1, 1], [l1, l2]], dtype=complex)
+    Psi = np.array([[l2, -1], [-l1, 1]], dtype=complex) / (l2 - l1)
+    A1 = np.array([[0.0, 1.0], [-w * w, -2 * z * w]])
+    A2 = np.zeros((2, 3))
+    A2[1, I.colex_rank((0, 0))] = -2.0 * kappa      # d^2 f_2 / dx_1^2
+    s = I.System("osc", 2, lam, Phi, Psi, A1, {2: A2}, {2: None}, delta=delta)
+    assert np.abs(Psi @ A1 @ Phi - np.diag(lam)).max() < 1e-14
+    if method == "full":
+        P = oracle.full(s, 2)["P"]
+    else:
+        P = oracle.sym(s, 2)["P"]
+    P_exp = np.zeros((2, 2), complex)
+    for j in range(2):
+        for k in range(2):
+            zeta = delta * Psi[:, k]
+            acc = 0
+            for p in range(2):
+                for q in range(2):
+                    acc += (-kappa * Psi[j, 1]) / (lam[p] + lam[q] - lam[j]) * zeta[p] * zeta[q]
+            P_exp[j, k] = -acc
+    assert rel(P, P_exp) < 1e-14
+    npf = oracle.assemble(s, P)
+    exp = np.array([[Phi[k, i] * (delta * Psi[i, k] + P_exp[i, k]) for i in range(2)]
+                    for k in range(2)])
+    assert rel(npf, exp) < 1e-14
+
+
+# ------------------------------------------------------------------ P7
+def _poly_field(A1, AM_full, M, x):
+    """f(x) = A1 x + (1/M!) A_M[x, .., x], evaluated by contracting with x M times."""
+    n = A1.shape[0]
+    T = AM_full.reshape((n,) * (M + 1)).astype(complex)
+    for _ in range(M):
+        T = T @ x
+    return A1 @ x + T / math.factorial(M)
+
+
+@pytest.mark.parametrize("n,M", [(3, 2), (4, 2), (3, 3), (4, 3), (3, 4)])
+def test_p7_polarization_finite_differences(n, M):
+    s = small(n, M, 71 + 10 * n + M)
+    AM_full = oracle.unpack_full(s.A[M], n, M)
+    C = oracle.sym(s, M, want_C=True)["C"]
+
+    def g(y):
+        return s.U @ _poly_field(s.A1, AM_full, M, s.V @ y) - s.lam * y
+
+    tups = I.sorted_tuples(n, M)
+    C_fd = np.zeros_like(C)
+    for r, t in enumerate(tups):
+        acc = np.zeros(n, complex)
+        for size in range(1, M + 1):
+            for S in itertools.combinations(range(M), size):
+                y = np.zeros(n, complex)
+                for i in S:
+                    y[t[i]] += 1.0
+                acc += (-1) ** (M - size) * g(y)
+        C_fd[:, r] = acc / math.factorial(M)
+    assert rel(C, C_fd) < 1e-11
+
+
+# ------------------------------------------------------------------ P8
+def _h_eval(hfull, M, z):
+    n = z.shape[0]
+    T = hfull.reshape((n,) * (M + 1))
+    for _ in range(M):
+        T = T @ z
+    return T
+
+
+def _h_jac(hfull, M, z):
+    n = z.shape[0]
+    T = hfull.reshape((n,) * (M + 1))
+    for _ in range(M - 1):
+        T = T @ z
+    return M * T                      # h is symmetric in its lower indices
+
+
+@pytest.mark.parametrize("M", [2, 3])
+def test_p8_homological_residual_order(M):
+    n = 4
+    s = small(n, M, 81 + M)
+    h = oracle.full(s, M)["h"]
+    AM_full = oracle.unpack_full(s.A[M], n, M)
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    w /= np.linalg.norm(w)
+    scales = np.array([0.1, 0.05, 0.025, 0.0125])
+    res = []
+    for sc in scales:
+        z = sc * w
+        y = z + _h_eval(h, M, z)
+        rhs = s.U @ _poly_field(s.A1, AM_full, M, s.V @ y)
+        zdot = np.linalg.solve(np.eye(n) + _h_jac(h, M, z), rhs)
+        res.append(np.linalg.norm(zdot - s.lam * z))
+    slope = np.polyfit(np.log(scales), np.log(res), 1)[0]
+    assert abs(slope - (2 * M - 1)) < 0.3, slope
+    # A wrong h (sign flipped) leaves the order-M residual in place.
+    res_bad = []
+    for sc in scales:
+        z = sc * w
+        y = z - _h_eval(h, M, z)
+        rhs = s.U @ _poly_field(s.A1, AM_full, M, s.V @ y)
+        zdot = np.linalg.solve(np.eye(n) - _h_jac(h, M, z), rhs)
+        res_bad.append(np.linalg.norm(zdot - s.lam * z))
+    slope_bad = np.polyfit(np.log(scales), np.log(res_bad), 1)[0]
+    assert abs(slope_bad - M) < 0.3, slope_bad
+
+
+# ------------------------------------------------------------------ P10
+@pytest.mark.parametrize("n,M", [(2, 2), (5, 2), (8, 2), (3, 3), (6, 3), (8, 3), (4, 4), (6, 4)])
+def test_p10_full_equals_sym(n, M):
+    s = small(n, M, 101 + 10 * n + M)
+    f = oracle.full(s, M)
+    y = oracle.sym(s, M, want_C=True, want_h=True)
+    assert rel(y["C"], full_to_sorted(f["C"], n, M)) < 1e-13
+    assert rel(y["h"], full_to_sorted(f["h"], n, M)) < 1e-13
+    assert rel(y["P"], f["P"]) < 1e-13
+
+
+def test_p10_mode_subset_rows_match():
+    s = I.block_sparse_system(12, [3], 5)
+    allm = oracle.sym(s, 3, want_h=True)
+    sub = oracle.sym(s, 3, modes=[7, 2], want_h=True)
+    assert np.array_equal(sub["P"], allm["P"][[7, 2]])
+    assert np.array_equal(sub["h"], allm["h"][[7, 2]])
+
+
+# ------------------------------------------------------------------ clamp (Alg. 2 step 9)
+def test_clamp_exact_resonance():
+    """Dyadic eigenvalues make lam_0 + lam_0 - lam_1 exactly 0: the clamp sets D = eps."""
+    n = 2
+    lam = np.array([-0.25 + 0.5j, -0.5 + 1.0j])
+    A2 = np.zeros((n, 3))
+    A2[1, 0] = 1.0                    # only (k=1; 0,0)
+    eps = 1e-3
+    s = I.System("res", n, lam, np.eye(n, dtype=complex), np.eye(n, dtype=complex),
+                 np.real(np.diag(lam)), {2: A2}, {2: None}, eps=eps)
+    out = oracle.sym(s, 2, want_C=True, want_h=True)
+    assert out["h"][1, 0] == out["C"][1, 0] / eps == 0.5 / eps
+
+
+def test_invalid_arguments_rejected():
+    s = small(3, 2, 1)
+    s.eps = 0.0
+    with pytest.raises(ValueError):
+        oracle.sym(s, 2)
+    s.eps = 1e-9
+    with pytest.raises(ValueError):
+        oracle.sym(s, 2, modes=[3])
