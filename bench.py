@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the NPF hot path on one MI355X.
+
+One step = one pass of the whole hot path over the workload: plan (Alg. 1 block sizing),
+upper-index contraction, the lower-index chain, divisor / division, reduction to P_M
+for every order, and the NPF assembly (Alg. 2), with inputs already resident in HBM.
+
+Prints ONE JSON line: modal tensor entries per second (sum over orders of n * U_M
+symmetric-unique entries per step / step time) for the selected precision, the same for
+the plain FP64 GPU path, the error of both against the CPU FP64 oracle, the roofline of
+the dominant kernel (timed live with HIP events on its launch stream) and the oracle's
+own rate on the host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "modal tensor entries/s + MFMA util, split-BF16 vs FP64 GPU at ≤1e-6 rel err"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA, MI355X
+PEAK_VALU_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}
+HBM_GBPS = 8000.0
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}
+SPLIT_PRODUCTS = {"fp64": 1, "fp32": 1, "bf16x3": 6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_work(name, sysm, plan):
+    """(algorithmic flops, algorithmic HBM bytes, bound, uses MFMA) of ONE launch of a
+    kernel, from the shapes (a complex multiply-add counts 8 flops, real x complex 4)."""
+    n, J, U = sysm.n, plan.block_modes, plan.unique_tuples
+    if name == "finalize":
+        return 8.0 * n * n, 16.0 * 4 * n * n, "hbm", False
+    M = int(name[1])
+    what = name.split("_", 1)[1]
+    if what == "psi_a":
+        t = sysm.tensors[M - 2]
+        if t.kind == 1:
+            nnz = int(t.desc.nnz)
+            return 4.0 * nnz * J, 8.0 * nnz + 8.0 * J * U[M], "alu", False
+        return 4.0 * n * J * U[M], 8.0 * n * U[M], "alu", False
+    if what.startswith("stage"):
+        i = int(what[5:])
+        return (8.0 * J * n * U[i] * U[M - i], 8.0 * J * (U[i - 1] * U[M - i + 1] + U[i] * U[M - i]),
+                "alu", False)
+    if what == "last_to_c":
+        return 8.0 * J * n * U[M], 8.0 * J * (U[M - 1] * n) + 16.0 * J * U[M], "alu", False
+    if what == "normal_form":
+        return 20.0 * J * U[M], 32.0 * J * U[M], "hbm", False
+    if what == "assemble":
+        return 8.0 * J * n * U[M], 16.0 * J * U[M], "alu", False
+    if what == "fused":
+        return 16.0 * J * n * U[M], 8.0 * J * U[M - 1] * n, "mfma", True
+    return 0.0, 0.0, "alu", False
+
+
+def time_path(sysm, s, precision, steps, warmup, device, profile):
+    import torch
+    from paper_2509_08968_amd import binding as B
+
+    n, N = s.n, s.order_max
+    P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
+    npf = torch.empty((n, n), dtype=torch.complex128, device=device)
+    mk = lambda: B.Plan(n, N, precision, s.eps, s.tau, s.delta)
+    plan0 = mk()
+    ws = plan0.workspace(device)
+    stream = torch.cuda.current_stream()
+
+    def step(plan):
+        plan.run(sysm.tensors, sysm.U, sysm.V, sysm.lam, ws, P, npf, stream)
+
+    for _ in range(warmup):
+        p = mk()
+        step(p)
+        p.close()
+    torch.cuda.synchronize()
+    plans = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        p = mk()                       # Alg. 1 block sizing is part of every step
+        if profile:
+            p.profile(True)
+        step(p)
+        plans.append(p)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    ktimes = {}
+    for p in plans:
+        if profile:
+            for k, (cnt, tot) in p.kernel_times().items():
+                c0, t_ = ktimes.get(k, (0, 0.0))
+                ktimes[k] = (c0 + cnt, t_ + tot)
+    for p in plans:
+        p.close()
+    out = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "kernels": ktimes,
+           "P": {M: P[M - 2].cpu().numpy() for M in range(2, N + 1)}, "npf": npf.cpu().numpy(),
+           "plan": plan0}
+    return out
+
+
+def rel(a, b):
+    import numpy as np
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def cpu_baseline(s, entries, target_s=10.0):
+    """The oracle as it stands, timed on this host's cores over a bounded sample: the full
+    workload, repeated until about target_s seconds of CPU time have passed."""
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        for M in s.orders:
+            oracle.sym(s, M, nthreads=cores)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or reps >= 1000:
+            break
+    return {"value": entries * reps / el, "unit": "modal entries/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"full workload (all output modes, orders {s.orders}) x {reps} repeats, "
+                      f"{el:.1f} s, packed-symmetric FP64 oracle with {cores} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n64-o3-blocksparse")
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the hot path is not sharded across GPUs in this "
+              "build (the design for sharding by output mode is described in DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2509_08968_amd import binding as B
+    from paper_2509_08968_amd import inputs as I
+
+    device = "cuda:0"
+    torch.cuda.set_device(0)
+    B.lib()
+    s = I.WORKLOADS[args.workload]()
+    sysm = B.upload_system(s, device)
+    log(f"[bench] workload {args.workload}: n={s.n} orders={s.orders}")
+
+    # Oracle reference (outside every timed region).
+    t0 = time.perf_counter()
+    refP = {M: oracle.sym(s, M)["P"] for M in s.orders}
+    ref_npf = oracle.assemble(s, sum(refP.values()))
+    log(f"[bench] oracle reference in {time.perf_counter() - t0:.1f} s")
+
+    res = time_path(sysm, s, args.precision, args.steps, args.warmup, device,
+                    not args.no_profile)
+    plan = res["plan"]
+    entries = plan.modal_entries
+    value = entries / (res["ms_per_step"] * 1e-3)
+    err = {f"P{M}": rel(res["P"][M], refP[M]) for M in s.orders}
+    err["npf"] = rel(res["npf"], ref_npf)
+    log(f"[bench] {args.precision}: {res['ms_per_step']:.3f} ms/step, {value:.3e} entries/s, err {err}")
+
+    fp64 = None
+    if args.precision != "fp64" and not args.no_fp64:
+        r64 = time_path(sysm, s, "fp64", args.steps, args.warmup, device, False)
+        v64 = entries / (r64["ms_per_step"] * 1e-3)
+        e64 = {f"P{M}": rel(r64["P"][M], refP[M]) for M in s.orders}
+        e64["npf"] = rel(r64["npf"], ref_npf)
+        fp64 = {"value": v64, "ms_per_step": r64["ms_per_step"], "rel_err": e64,
+                "speedup_of_selected": v64 and value / v64}
+        log(f"[bench] fp64: {r64['ms_per_step']:.3f} ms/step, {v64:.3e} entries/s, err {e64}")
+
+    roof = None
+    if res["kernels"]:
+        name, (cnt, tot) = max(res["kernels"].items(), key=lambda kv: kv[1][1])
+        flops, byts, bound, mfma = kernel_work(name, sysm, plan)
+        avg_s = tot / cnt * 1e-3
+        if bound == "hbm":
+            achieved, peak, unit = byts / avg_s / 1e9, HBM_GBPS, "GB/s"
+        else:
+            achieved = flops / avg_s / 1e12
+            peak = (PEAK_TFLOPS if mfma else PEAK_VALU_TFLOPS)[args.precision]
+            unit = "TFLOP/s"
+        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": None, "kernel": name,
+                "avg_launch_ms": tot / cnt, "launches_per_step": cnt / args.steps,
+                "share_of_step": tot / args.steps / res["ms_per_step"]}
+        if mfma:
+            roof["executed_mfma_frac"] = achieved * SPLIT_PRODUCTS[args.precision] / peak
+        log(f"[bench] kernels: " + ", ".join(f"{k}={v[1] / args.steps:.3f}ms"
+                                             for k, v in sorted(res['kernels'].items())))
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(s, entries)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "modal entries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[args.precision], "data": "synthetic",
+        "config": {"workload": args.workload, "n": s.n, "orders": s.orders,
+                   "precision": args.precision, "modal_entries_per_step": entries,
+                   "block_modes": plan.block_modes, "blocks": plan.n_blocks},
+        "rel_err_vs_oracle": err,
+        "fp64_gpu": fp64,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

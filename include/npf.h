@@ -1,0 +1,172 @@
+/*
+ * npf.h -- C ABI of the MI355X (gfx950) library for high-order nonlinear participation
+ * factors (NPFs) by batched tensor contraction (Sajjadi, Huang, Sun, arXiv 2509.08968).
+ *
+ * The library runs the hot path of the paper's vectorized method (Alg. 2) for one
+ * diagonalizable system with n states, orders M = 2..N:
+ *
+ *   C_M[j,t] = (1/M!) sum_k Psi[j,k] sum_{a} A_M[k,a] Phi[a_1,t_1] .. Phi[a_M,t_M]
+ *                                                  (Alg. 2 steps 1-4; eq. (4) numerator)
+ *   D_M[j,t] = (lam[t_1] + .. + lam[t_M]) - lam[j],  |D| < eps -> D = eps (steps 5-9)
+ *   h_M[j,t] = C_M[j,t] / D_M[j,t]                   (step 11; eq. (4))
+ *   P_M[j,k] = - sum_{t in [n]^M} h_M[j,t] prod_i delta Psi[t_i,k]   (steps 12-19; eq. (7))
+ *   NPF[k,i] = Phi[k,i] (delta Psi[i,k] + sum_{M=2..N} P_M[i,k])      (step 20; eq. (7))
+ *
+ * with Phi the right eigenvectors (columns), Psi = Phi^{-1} the left eigenvectors (rows),
+ * lam the eigenvalues, A_M the M-th derivative tensor of the vector field at the
+ * equilibrium (eq. (1)), symmetric in its M lower indices, and delta the excitation
+ * magnitude of the kicked state (eq. (6)-(7)).
+ *
+ * Conventions
+ *   - Sizes are int64_t.  Every array pointer passed to a compute call is a DEVICE pointer
+ *     owned by the caller; the library never allocates or frees device memory.
+ *   - Complex arrays are interleaved (re, im) double pairs (complex128), row-major:
+ *       Phi[a*n + i] = Phi[state a, mode i];  Psi[i*n + k] = Psi[mode i, state k];
+ *       lam[i];  P[j*n + k] (mode j, state k);  NPF[k*n + i] (state k, mode i).
+ *   - Symmetric tensors are packed over sorted index tuples t_1 <= .. <= t_M (0-based) at
+ *     the colex rank r(t) = sum_{i=1..M} binom(t_i + i - 1, i), so an order-M tensor over
+ *     n states has U_M = binom(n + M - 1, M) entries per upper index.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Compute calls
+ *     only enqueue work and return; they are ordered on `stream`.
+ *   - Errors: calls return NPF_OK (0) or an NPF_E_* code.  Argument errors are found
+ *     before anything is enqueued and nothing is written.  NPF_E_DEVICE reports a HIP
+ *     launch error.  npf_last_error() gives a message for the calling thread.
+ *   - A plan is an opaque host object holding only host metadata; it may be shared by
+ *     calls on different streams, but calls that share a workspace must be serialised.
+ */
+#ifndef NPF_H
+#define NPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NPF_OK 0
+#define NPF_E_INVALID 1     /* bad argument, shape or size                        */
+#define NPF_E_BUDGET 2      /* the memory budget is below the smallest block      */
+#define NPF_E_DEVICE 3      /* a HIP call or kernel launch failed                 */
+#define NPF_E_UNSUPPORTED 4 /* valid request this build cannot serve              */
+
+#define NPF_MAX_ORDER 6     /* largest N                                           */
+#define NPF_ALL_BLOCKS (-1)
+
+/* Arithmetic of the contractions (the divisor and the NPF accumulation are always FP64). */
+#define NPF_FP64 0          /* FP64 operands, FP64 accumulation                    */
+#define NPF_FP32 1          /* FP32 operands, FP32 accumulation per tile           */
+#define NPF_BF16X3 2        /* FP32 values split in three BF16 terms, six products
+                               per multiply, FP32 accumulation per tile            */
+
+/* Storage of one derivative tensor A_M (device memory). */
+#define NPF_SRC_DENSE 0     /* values[k*U_M + r]                                   */
+#define NPF_SRC_SPARSE 1    /* compressed by sorted tuple: for c in [0, ncols):
+                               rank col_rank[c], entries col_ptr[c]..col_ptr[c+1]-1
+                               with state row_k[e] and value values[e]            */
+
+typedef struct npf_tensor {
+    int32_t kind;
+    int32_t order;             /* M                                                  */
+    const double *values;      /* dense [n*U_M] or sparse [nnz]                      */
+    const int64_t *col_rank;   /* sparse: [ncols], strictly increasing               */
+    const int64_t *col_ptr;    /* sparse: [ncols+1], col_ptr[0] = 0                  */
+    const int32_t *row_k;      /* sparse: [nnz], 0 <= row_k < n                       */
+    int64_t ncols;
+    int64_t nnz;
+} npf_tensor;
+
+/* Problem description (host memory; copied by npf_plan_create). */
+typedef struct npf_problem {
+    int64_t n;                 /* states = modes, n >= 1                              */
+    int32_t order_max;         /* N, 2 <= N <= NPF_MAX_ORDER                          */
+    int32_t precision;         /* NPF_FP64 / NPF_FP32 / NPF_BF16X3                    */
+    double eps;                /* divisor clamp of Alg. 2 step 9, > 0                 */
+    double tau;                /* mixed paths divide in FP64 when |D| < tau, >= 0     */
+    double delta;              /* excitation magnitude of eq. (7)                     */
+    int64_t hbm_budget_bytes;  /* workspace cap, the M_limit of Alg. 1; 0 = none      */
+    int64_t block_modes;       /* output modes per block; 0 = chosen by the planner   */
+} npf_problem;
+
+typedef struct npf_plan_s *npf_plan_t;
+
+typedef struct npf_plan_report {
+    int64_t n;
+    int32_t order_max;
+    int32_t precision;
+    int64_t workspace_bytes;           /* size of `ws` for every compute call          */
+    int64_t block_modes;               /* J: output modes per block                    */
+    int64_t n_blocks;                  /* ceil(n / J)  (the BC of Alg. 1 for mode j)   */
+    int64_t unique_tuples[NPF_MAX_ORDER + 1];   /* U_M per order                       */
+    int64_t modal_entries;             /* sum_M n * U_M, symmetric-unique entries      */
+} npf_plan_report;
+
+/* Plan (host only, synchronous): validates the problem, fixes the output-mode block size
+ * J under hbm_budget_bytes following the batch-size rule of Alg. 1 (steps 6-15) and the
+ * workspace size.  Returns NPF_E_BUDGET if even the smallest block does not fit. */
+int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out);
+int npf_plan_info(npf_plan_t plan, npf_plan_report *report);
+void npf_plan_destroy(npf_plan_t plan);
+
+/* Alg. 2 steps 1-4 for output-mode block `block` (modes [block*J, min(n, block*J+J)))
+ * of order M: writes C_out[jj*U_M + r] (complex128, jj = j - block*J) for the block's
+ * modes and every sorted tuple r.  U, V: Psi, Phi as above.  ws: device workspace of at
+ * least workspace_bytes.  The contraction runs in the plan's precision. */
+int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block, const npf_tensor *A,
+                       const void *U, const void *V, void *ws, int64_t ws_bytes,
+                       void *C_out, void *stream);
+
+/* Alg. 2 steps 5-11 in place on the block's C (as written by npf_modal_contract):
+ * h = C / D with D = (lam[t_1] + .. + lam[t_M]) - lam[j] summed in FP64 over the sorted
+ * tuple left to right; |D|^2 < eps^2 (FP64, no fused multiply-add) sets D = eps. */
+int npf_normal_form(npf_plan_t plan, int32_t order, int64_t block, const void *lambda,
+                    void *C_inout, void *stream);
+
+/* Alg. 2 steps 12-19 for the block: P_acc[j*n + k] += -sum_{sorted t} m(t) h[j,t]
+ * prod_i delta Psi[t_i,k], with m(t) the number of orderings of t; FP64. */
+int npf_assemble(npf_plan_t plan, int32_t order, int64_t block, const void *h,
+                 const void *U, void *P_acc, void *stream);
+
+/* Alg. 2 step 20: NPF[k*n + i] = Phi[k,i] (delta Psi[i,k] + P_sum[i*n + k]).
+ * P_sum may be NULL (the linear participation factors). */
+int npf_finalize(npf_plan_t plan, const void *U, const void *V, const void *P_sum,
+                 void *npf_out, void *stream);
+
+/* The whole hot path, all orders 2..N and all blocks, with the last contraction, the
+ * divisor, the division and the reduction fused: A[M-2] describes A_M.  Writes
+ * P_out[(M-2)*n*n + j*n + k] (nullable) and NPF (nullable).  Deterministic: two calls on
+ * the same inputs give bitwise equal results. */
+int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
+            const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
+            void *stream);
+
+/* Alg. 1 (batched derivative tensor) arithmetic, host only: for a tensor with n_dim
+ * dimensions of extent n_s, bytes_per_entry bytes per entry and a limit of m_limit_gb
+ * GiB per batch, writes the batch count per dimension BC[n_dim], the largest batch
+ * extent per dimension max_batch[n_dim], the total size in GiB and the size of one batch
+ * in GiB.  Returns the number of batches prod(BC), or -1 on bad arguments. */
+int64_t npf_alg1_batches(int32_t n_dim, int64_t n_s, double m_limit_gb, int32_t bytes_per_entry,
+                         int64_t *BC, int64_t *max_batch, double *total_gb, double *batch_gb);
+
+/* Kernel timing (host, for measurement).  npf_plan_profile(plan, 1) clears earlier records
+ * and makes later compute calls with this plan record a HIP event pair around every kernel
+ * launch, on the launch stream; npf_plan_profile(plan, 0) stops recording.
+ * npf_plan_kernel_times waits for the recorded events and writes, per kernel name, the
+ * number of launches and their summed duration in milliseconds (at most `capacity`
+ * entries; *count receives the number of names). */
+typedef struct npf_kernel_time {
+    char name[40];
+    int64_t launches;
+    double total_ms;
+} npf_kernel_time;
+
+int npf_plan_profile(npf_plan_t plan, int32_t enable);
+int npf_plan_kernel_times(npf_plan_t plan, npf_kernel_time *out, int32_t capacity,
+                          int32_t *count);
+
+const char *npf_error_string(int code);
+const char *npf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,306 @@
+"""ctypes binding of libnpf.so (the C ABI in include/npf.h).
+
+Argument marshalling only: torch supplies device memory and the HIP stream, every step of
+the hot path runs in the library's HIP kernels.  Importing this module does not need a
+GPU; loading the library fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnpf.so")
+
+NPF_OK, NPF_E_INVALID, NPF_E_BUDGET, NPF_E_DEVICE, NPF_E_UNSUPPORTED = 0, 1, 2, 3, 4
+NPF_MAX_ORDER = 6
+NPF_ALL_BLOCKS = -1
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+SRC_DENSE, SRC_SPARSE = 0, 1
+
+EXPORTED = [
+    "npf_plan_create", "npf_plan_info", "npf_plan_destroy", "npf_modal_contract",
+    "npf_normal_form", "npf_assemble", "npf_finalize", "npf_run", "npf_alg1_batches",
+    "npf_plan_profile", "npf_plan_kernel_times", "npf_error_string", "npf_last_error",
+]
+
+
+class NpfError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: error {code}: {msg}")
+        self.code = code
+
+
+class NpfTensor(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("values", ctypes.c_void_p), ("col_rank", ctypes.c_void_p),
+        ("col_ptr", ctypes.c_void_p), ("row_k", ctypes.c_void_p),
+        ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+    ]
+
+
+class NpfKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+class NpfProblem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("order_max", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("tau", ctypes.c_double), ("delta", ctypes.c_double),
+        ("hbm_budget_bytes", ctypes.c_int64), ("block_modes", ctypes.c_int64),
+    ]
+
+
+class NpfPlanReport(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("order_max", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_int64), ("block_modes", ctypes.c_int64),
+        ("n_blocks", ctypes.c_int64),
+        ("unique_tuples", ctypes.c_int64 * (NPF_MAX_ORDER + 1)),
+        ("modal_entries", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libnpf.so.  Raises if it is missing: there is no fallback path."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2509_08968_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.npf_plan_create.argtypes = [ctypes.POINTER(NpfProblem), ctypes.POINTER(P)]
+        L.npf_plan_info.argtypes = [P, ctypes.POINTER(NpfPlanReport)]
+        L.npf_plan_destroy.argtypes = [P]
+        L.npf_plan_destroy.restype = None
+        L.npf_modal_contract.argtypes = [P, i32, i64, ctypes.POINTER(NpfTensor), P, P, P, i64, P, P]
+        L.npf_normal_form.argtypes = [P, i32, i64, P, P, P]
+        L.npf_assemble.argtypes = [P, i32, i64, P, P, P, P]
+        L.npf_finalize.argtypes = [P, P, P, P, P, P]
+        L.npf_run.argtypes = [P, ctypes.POINTER(NpfTensor), P, P, P, P, i64, P, P, P]
+        L.npf_alg1_batches.argtypes = [i32, i64, dbl, i32, ctypes.POINTER(i64),
+                                       ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                       ctypes.POINTER(dbl)]
+        L.npf_alg1_batches.restype = i64
+        L.npf_plan_profile.argtypes = [P, i32]
+        L.npf_plan_kernel_times.argtypes = [P, ctypes.POINTER(NpfKernelTime), i32,
+                                            ctypes.POINTER(i32)]
+        L.npf_error_string.argtypes = [ctypes.c_int]
+        L.npf_error_string.restype = ctypes.c_char_p
+        L.npf_last_error.argtypes = []
+        L.npf_last_error.restype = ctypes.c_char_p
+        for f in ("npf_plan_create", "npf_plan_info", "npf_modal_contract", "npf_normal_form",
+                  "npf_assemble", "npf_finalize", "npf_run", "npf_plan_profile",
+                  "npf_plan_kernel_times"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != NPF_OK:
+        raise NpfError(rc, where, lib().npf_last_error().decode())
+
+
+def alg1_batches(n_dim: int, n_s: int, m_limit_gb: float, bytes_per_entry: int = 8):
+    """Alg. 1 arithmetic (host only): batch count and largest batch per dimension."""
+    BC = (ctypes.c_int64 * n_dim)()
+    mb = (ctypes.c_int64 * n_dim)()
+    tot, per = ctypes.c_double(), ctypes.c_double()
+    nb = lib().npf_alg1_batches(n_dim, n_s, m_limit_gb, bytes_per_entry, BC, mb,
+                                ctypes.byref(tot), ctypes.byref(per))
+    if nb < 0:
+        raise ValueError("npf_alg1_batches rejected its arguments")
+    return {"batches": int(nb), "BC": list(BC), "max_batch": list(mb),
+            "total_gb": tot.value, "batch_gb": per.value}
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """Owns an npf_plan_t (host metadata only)."""
+
+    def __init__(self, n: int, order_max: int, precision: str = "fp64", eps: float = 1e-9,
+                 tau: float = 1e-2, delta: float = 1.0, budget_bytes: int = 0,
+                 block_modes: int = 0):
+        prob = NpfProblem(n, order_max, PRECISIONS[precision], eps, tau, delta, budget_bytes,
+                          block_modes)
+        h = ctypes.c_void_p()
+        _check(lib().npf_plan_create(ctypes.byref(prob), ctypes.byref(h)), "npf_plan_create")
+        self._h = h
+        self.n, self.order_max, self.precision = n, order_max, precision
+        r = NpfPlanReport()
+        _check(lib().npf_plan_info(self._h, ctypes.byref(r)), "npf_plan_info")
+        self.workspace_bytes = r.workspace_bytes
+        self.block_modes = r.block_modes
+        self.n_blocks = r.n_blocks
+        self.unique_tuples = list(r.unique_tuples)
+        self.modal_entries = r.modal_entries
+
+    def close(self):
+        if self._h:
+            lib().npf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every kernel launch of later calls (on their stream)."""
+        _check(lib().npf_plan_profile(self._h, 1 if enable else 0), "npf_plan_profile")
+
+    def kernel_times(self):
+        """{kernel name: (launches, total ms)} of the recorded launches (waits for them)."""
+        cap = 256
+        arr = (NpfKernelTime * cap)()
+        cnt = ctypes.c_int32()
+        _check(lib().npf_plan_kernel_times(self._h, arr, cap, ctypes.byref(cnt)),
+               "npf_plan_kernel_times")
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms)
+                for i in range(min(cnt.value, cap))}
+
+    def workspace(self, device):
+        import torch
+        return torch.empty(max(self.workspace_bytes, 1), dtype=torch.uint8, device=device)
+
+    def modal_contract(self, order, block, A: "DeviceTensor", U, V, ws, C_out, stream=None):
+        _check(lib().npf_modal_contract(self._h, order, block, ctypes.byref(A.desc), _ptr(U),
+                                        _ptr(V), _ptr(ws), ws.numel(), _ptr(C_out),
+                                        _stream(stream)), "npf_modal_contract")
+
+    def normal_form(self, order, block, lam, C, stream=None):
+        _check(lib().npf_normal_form(self._h, order, block, _ptr(lam), _ptr(C), _stream(stream)),
+               "npf_normal_form")
+
+    def assemble(self, order, block, h, U, P_acc, stream=None):
+        _check(lib().npf_assemble(self._h, order, block, _ptr(h), _ptr(U), _ptr(P_acc),
+                                  _stream(stream)), "npf_assemble")
+
+    def finalize(self, U, V, P_sum, npf_out, stream=None):
+        _check(lib().npf_finalize(self._h, _ptr(U), _ptr(V), _ptr(P_sum), _ptr(npf_out),
+                                  _stream(stream)), "npf_finalize")
+
+    def run(self, tensors: List["DeviceTensor"], U, V, lam, ws, P_out=None, npf_out=None,
+            stream=None):
+        arr = (NpfTensor * len(tensors))(*[t.desc for t in tensors])
+        _check(lib().npf_run(self._h, arr, _ptr(U), _ptr(V), _ptr(lam), _ptr(ws), ws.numel(),
+                             _ptr(P_out), _ptr(npf_out), _stream(stream)), "npf_run")
+
+
+@dataclass
+class DeviceTensor:
+    """Device copy of one packed derivative tensor and its npf_tensor descriptor."""
+    order: int
+    kind: int
+    tensors: Dict[str, object] = field(default_factory=dict)
+    desc: NpfTensor = None
+
+
+def sparse_columns(A: np.ndarray, support: Optional[np.ndarray] = None):
+    """Compress a packed tensor [n, U_M] by sorted tuple: (col_rank, col_ptr, row_k, values)."""
+    cols = np.arange(A.shape[1]) if support is None else np.asarray(support, np.int64)
+    sub = A[:, cols]
+    nz = sub != 0
+    keep = nz.any(axis=0)
+    cols, sub, nz = cols[keep], sub[:, keep], nz[:, keep]
+    counts = nz.sum(axis=0)
+    col_ptr = np.zeros(len(cols) + 1, np.int64)
+    np.cumsum(counts, out=col_ptr[1:])
+    kk, cc = np.nonzero(nz.T)           # column-major walk: by column, then state
+    row_k = cc.astype(np.int32)
+    values = sub.T[kk, cc].astype(np.float64)
+    return cols.astype(np.int64), col_ptr, row_k, values
+
+
+def _at_least_one(a: np.ndarray) -> np.ndarray:
+    return a if a.size else np.zeros(1, a.dtype)
+
+
+def upload_tensor(A: np.ndarray, order: int, device, sparse: bool = False,
+                  support: Optional[np.ndarray] = None) -> DeviceTensor:
+    import torch
+    if not sparse:
+        vals = torch.from_numpy(np.ascontiguousarray(A, np.float64)).to(device)
+        desc = NpfTensor(SRC_DENSE, order, vals.data_ptr(), None, None, None, 0, 0)
+        return DeviceTensor(order, SRC_DENSE, {"values": vals}, desc)
+    cols, ptr, rows, vals = sparse_columns(A, support)
+    t = {
+        "values": torch.from_numpy(_at_least_one(vals)).to(device),
+        "col_rank": torch.from_numpy(_at_least_one(cols)).to(device),
+        "col_ptr": torch.from_numpy(ptr).to(device),
+        "row_k": torch.from_numpy(_at_least_one(rows)).to(device),
+    }
+    desc = NpfTensor(SRC_SPARSE, order, t["values"].data_ptr(), t["col_rank"].data_ptr(),
+                     t["col_ptr"].data_ptr(), t["row_k"].data_ptr(), len(cols), len(vals))
+    return DeviceTensor(order, SRC_SPARSE, t, desc)
+
+
+@dataclass
+class DeviceSystem:
+    n: int
+    lam: object
+    U: object
+    V: object
+    tensors: List[DeviceTensor]
+    orders: List[int]
+
+
+def upload_system(sys, device, sparse: Optional[bool] = None) -> DeviceSystem:
+    """Copy one operating point (inputs.System) to the device."""
+    import torch
+
+    def c128(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.complex128)).to(device)
+
+    tens = []
+    for M in range(2, sys.order_max + 1):
+        A = sys.A.get(M)
+        if A is None:
+            A = np.zeros((sys.n, 1))
+            tens.append(upload_tensor(A, M, device, sparse=True, support=np.zeros(0, np.int64)))
+            continue
+        sp = sparse if sparse is not None else (sys.support.get(M) is not None)
+        tens.append(upload_tensor(A, M, device, sparse=sp, support=sys.support.get(M)))
+    return DeviceSystem(sys.n, c128(sys.lam), c128(sys.U), c128(sys.V), tens,
+                        list(range(2, sys.order_max + 1)))
+
+
+def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0,
+            block_modes: int = 0, sparse: Optional[bool] = None):
+    """Run the fused hot path on one system; returns (NPF, {M: P_M}) as numpy arrays."""
+    import torch
+    dev = upload_system(sys, device, sparse)
+    plan = Plan(sys.n, sys.order_max, precision, sys.eps, sys.tau, sys.delta, budget_bytes,
+                block_modes)
+    ws = plan.workspace(device)
+    n, N = sys.n, sys.order_max
+    P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
+    npf = torch.empty((n, n), dtype=torch.complex128, device=device)
+    plan.run(dev.tensors, dev.U, dev.V, dev.lam, ws, P, npf)
+    torch.cuda.synchronize(device)
+    Ps = {M: P[M - 2].cpu().numpy() for M in range(2, N + 1)}
+    out = npf.cpu().numpy()
+    plan.close()
+    return out, Ps

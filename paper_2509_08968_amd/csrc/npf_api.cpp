@@ -1,0 +1,217 @@
+// C ABI entry points: argument checks, block loops and kernel sequencing.
+#include <cstring>
+#include <string>
+
+#include "npf_internal.h"
+
+using namespace npf;
+
+namespace {
+
+int check_hip(hipError_t e, const char *where)
+{
+    if (e == hipSuccess) return NPF_OK;
+    return fail(NPF_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int check_tensor(const npf_plan_s *p, const npf_tensor *A, int M)
+{
+    if (!A) return fail(NPF_E_INVALID, "null tensor descriptor");
+    if (A->order != M) return fail(NPF_E_INVALID, "tensor order does not match the requested order");
+    if (A->kind == NPF_SRC_DENSE) {
+        if (!A->values) return fail(NPF_E_INVALID, "dense tensor without values");
+        return NPF_OK;
+    }
+    if (A->kind == NPF_SRC_SPARSE) {
+        if (!A->values || !A->col_rank || !A->col_ptr || !A->row_k)
+            return fail(NPF_E_INVALID, "sparse tensor with a null array");
+        if (A->ncols < 0 || A->ncols > p->U[M] || A->nnz < 0)
+            return fail(NPF_E_INVALID, "sparse tensor sizes out of range");
+        return NPF_OK;
+    }
+    return fail(NPF_E_INVALID, "unknown tensor kind");
+}
+
+int check_order_block(const npf_plan_s *p, int32_t order, int64_t block)
+{
+    if (order < 2 || order > p->N) return fail(NPF_E_INVALID, "order outside [2, order_max]");
+    if (block != NPF_ALL_BLOCKS && (block < 0 || block >= p->n_blocks))
+        return fail(NPF_E_INVALID, "block index out of range");
+    return NPF_OK;
+}
+
+// Blocks [b0, b1) selected by `block`.
+void block_range(const npf_plan_s *p, int64_t block, int64_t &b0, int64_t &b1)
+{
+    if (block == NPF_ALL_BLOCKS) {
+        b0 = 0;
+        b1 = p->n_blocks;
+    } else {
+        b0 = block;
+        b1 = block + 1;
+    }
+}
+
+void block_modes(const npf_plan_s *p, int64_t b, int64_t &j0, int64_t &J)
+{
+    j0 = b * p->J;
+    J = p->n - j0 < p->J ? p->n - j0 : p->J;
+}
+
+std::string kname(int M, const char *what, int i = -1)
+{
+    std::string s = "o" + std::to_string(M) + "_" + what;
+    if (i >= 0) s += std::to_string(i);
+    return s;
+}
+
+int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tensor *A,
+              const void *U, const void *V, void *ws, hipStream_t s)
+{
+    ChainArgs a{p, M, j0, J, A, static_cast<const double *>(U), static_cast<const double *>(V),
+                static_cast<char *>(ws), s};
+    int rc;
+    {
+        Timed t(p, kname(M, "psi_a"), s);
+        rc = check_hip(launch_psi_a(a), "upper-index contraction");
+    }
+    for (int i = 1; rc == NPF_OK && i < M; ++i) {
+        Timed t(p, kname(M, "stage", i), s);
+        rc = check_hip(launch_stage(a, i), "chain stage");
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block,
+                                  const npf_tensor *A, const void *U, const void *V, void *ws,
+                                  int64_t ws_bytes, void *C_out, void *stream)
+{
+    if (!plan) return fail(NPF_E_INVALID, "null plan");
+    int rc = check_order_block(plan, order, block);
+    if (rc) return rc;
+    if ((rc = check_tensor(plan, A, order))) return rc;
+    if (!U || !V || !ws || !C_out) return fail(NPF_E_INVALID, "null device pointer");
+    if (ws_bytes < plan->lay.total) return fail(NPF_E_INVALID, "workspace smaller than planned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t b0, b1;
+    block_range(plan, block, b0, b1);
+    for (int64_t b = b0; b < b1 && rc == NPF_OK; ++b) {
+        int64_t j0, J;
+        block_modes(plan, b, j0, J);
+        rc = run_chain(plan, order, j0, J, A, U, V, ws, s);
+        if (rc) break;
+        double *dst = static_cast<double *>(C_out) + 2 * (j0 - b0 * plan->J) * plan->U[order];
+        ChainArgs a{plan, order, j0, J, A, static_cast<const double *>(U),
+                    static_cast<const double *>(V), static_cast<char *>(ws), s};
+        rc = check_hip(launch_last_to_c(a, dst), "last contraction stage");
+    }
+    return rc;
+}
+
+extern "C" int npf_normal_form(npf_plan_t plan, int32_t order, int64_t block, const void *lambda,
+                               void *C_inout, void *stream)
+{
+    if (!plan) return fail(NPF_E_INVALID, "null plan");
+    int rc = check_order_block(plan, order, block);
+    if (rc) return rc;
+    if (!lambda || !C_inout) return fail(NPF_E_INVALID, "null device pointer");
+    int64_t b0, b1;
+    block_range(plan, block, b0, b1);
+    int64_t j0a, Ja, j0b, Jb;
+    block_modes(plan, b0, j0a, Ja);
+    block_modes(plan, b1 - 1, j0b, Jb);
+    return check_hip(launch_normal_form(plan, order, j0a, j0b + Jb - j0a,
+                                        static_cast<const double *>(lambda),
+                                        static_cast<double *>(C_inout),
+                                        static_cast<hipStream_t>(stream)),
+                     "normal form");
+}
+
+extern "C" int npf_assemble(npf_plan_t plan, int32_t order, int64_t block, const void *h,
+                            const void *U, void *P_acc, void *stream)
+{
+    if (!plan) return fail(NPF_E_INVALID, "null plan");
+    int rc = check_order_block(plan, order, block);
+    if (rc) return rc;
+    if (!h || !U || !P_acc) return fail(NPF_E_INVALID, "null device pointer");
+    int64_t b0, b1;
+    block_range(plan, block, b0, b1);
+    int64_t j0a, Ja, j0b, Jb;
+    block_modes(plan, b0, j0a, Ja);
+    block_modes(plan, b1 - 1, j0b, Jb);
+    return check_hip(launch_assemble(plan, order, j0a, j0b + Jb - j0a,
+                                     static_cast<const double *>(h),
+                                     static_cast<const double *>(U), static_cast<double *>(P_acc),
+                                     static_cast<hipStream_t>(stream)),
+                     "assemble");
+}
+
+extern "C" int npf_finalize(npf_plan_t plan, const void *U, const void *V, const void *P_sum,
+                            void *npf_out, void *stream)
+{
+    if (!plan) return fail(NPF_E_INVALID, "null plan");
+    if (!U || !V || !npf_out) return fail(NPF_E_INVALID, "null device pointer");
+    return check_hip(launch_finalize(plan, static_cast<const double *>(U),
+                                     static_cast<const double *>(V),
+                                     static_cast<const double *>(P_sum),
+                                     static_cast<double *>(npf_out),
+                                     static_cast<hipStream_t>(stream)),
+                     "finalize");
+}
+
+extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
+                       const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
+                       void *stream)
+{
+    if (!plan) return fail(NPF_E_INVALID, "null plan");
+    if (!A || !U || !V || !lambda || !ws) return fail(NPF_E_INVALID, "null argument");
+    if (ws_bytes < plan->lay.total) return fail(NPF_E_INVALID, "workspace smaller than planned");
+    int rc = NPF_OK;
+    for (int M = 2; M <= plan->N; ++M)
+        if ((rc = check_tensor(plan, &A[M - 2], M))) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    const int64_t nn = plan->n * plan->n;
+    double *psum = reinterpret_cast<double *>(w + plan->lay.psum);
+    double *cbuf = reinterpret_cast<double *>(w + plan->lay.cbuf);
+    double *pm = reinterpret_cast<double *>(w + plan->lay.pm);
+    for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
+        double *PM = P_out ? static_cast<double *>(P_out) + 2 * (M - 2) * nn : pm;
+        rc = check_hip(launch_zero(PM, 2 * nn, s), "zero P");
+        for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
+            int64_t j0, J;
+            block_modes(plan, b, j0, J);
+            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, s);
+            if (rc) break;
+            ChainArgs a{plan, M, j0, J, &A[M - 2], static_cast<const double *>(U),
+                        static_cast<const double *>(V), w, s};
+            {
+                Timed t(plan, kname(M, "last_to_c"), s);
+                rc = check_hip(launch_last_to_c(a, cbuf), "last contraction stage");
+            }
+            if (!rc) {
+                Timed t(plan, kname(M, "normal_form"), s);
+                rc = check_hip(launch_normal_form(plan, M, j0, J,
+                                                  static_cast<const double *>(lambda), cbuf, s),
+                               "normal form");
+            }
+            if (!rc) {
+                Timed t(plan, kname(M, "assemble"), s);
+                rc = check_hip(launch_assemble(plan, M, j0, J, cbuf,
+                                               static_cast<const double *>(U), PM, s),
+                               "assemble");
+            }
+        }
+        if (!rc) rc = check_hip(launch_accumulate(psum, PM, 2 * nn, M == 2, s), "sum over orders");
+    }
+    if (!rc && npf_out) {
+        Timed t(plan, "finalize", s);
+        rc = check_hip(launch_finalize(plan, static_cast<const double *>(U),
+                                       static_cast<const double *>(V), psum,
+                                       static_cast<double *>(npf_out), s),
+                       "finalize");
+    }
+    return rc;
+}

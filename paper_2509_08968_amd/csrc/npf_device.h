@@ -1,0 +1,127 @@
+// Device helpers: packed symmetric index arithmetic and the FP64 divisor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "npf.h"
+
+namespace npf {
+
+constexpr int kMaxOrder = NPF_MAX_ORDER;
+
+// binom(x + i - 1, i) for x >= 0, i >= 1: the colex weight of value x at position i.
+__host__ __device__ __forceinline__ int64_t colex_term(int64_t x, int i)
+{
+    int64_t r = x;
+    for (int s = 1; s < i; ++s) r = r * (x + s) / (s + 1);
+    return r;
+}
+
+// Colex rank of a sorted m-tuple.
+__host__ __device__ __forceinline__ int64_t colex_rank(const int32_t *t, int m)
+{
+    int64_t r = 0;
+    for (int i = 0; i < m; ++i) r += colex_term(t[i], i + 1);
+    return r;
+}
+
+// Sorted m-tuple over [0, n) with colex rank r (binary search per position).
+__host__ __device__ __forceinline__ void colex_unrank(int64_t r, int m, int64_t n, int32_t *t)
+{
+    for (int i = m; i >= 1; --i) {
+        int64_t lo = 0, hi = n - 1;  // largest x with colex_term(x, i) <= r
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (colex_term(mid, i) <= r) lo = mid; else hi = mid - 1;
+        }
+        t[i - 1] = int32_t(lo);
+        r -= colex_term(lo, i);
+    }
+}
+
+// Advance a sorted m-tuple over [0, n) to its colex successor; false after the last.
+__host__ __device__ __forceinline__ bool colex_next(int32_t *t, int m, int64_t n)
+{
+    for (int i = 0; i < m; ++i) {
+        const int64_t cap = (i + 1 < m) ? t[i + 1] : n - 1;
+        if (t[i] < cap) {
+            t[i] += 1;
+            for (int l = 0; l < i; ++l) t[l] = 0;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Colex rank of sort({a} U s) for a sorted m-tuple s.
+__host__ __device__ __forceinline__ int64_t colex_rank_insert(int32_t a, const int32_t *s, int m)
+{
+    int64_t r = 0;
+    int pos = 1;
+    bool placed = false;
+    for (int i = 0; i < m; ++i) {
+        if (!placed && a <= s[i]) {
+            r += colex_term(a, pos++);
+            placed = true;
+        }
+        r += colex_term(s[i], pos++);
+    }
+    if (!placed) r += colex_term(a, pos);
+    return r;
+}
+
+// Orderings of a sorted tuple: M! / prod(count_v!).
+__host__ __device__ __forceinline__ double multiplicity(const int32_t *s, int M)
+{
+    double f = 1.0;
+    for (int i = 2; i <= M; ++i) f *= double(i);
+    int run = 1;
+    double den = 1.0;
+    for (int i = 1; i <= M; ++i) {
+        if (i < M && s[i] == s[i - 1]) {
+            ++run;
+            den *= double(run);
+        } else {
+            run = 1;
+        }
+    }
+    return f / den;
+}
+
+// Small divisor of Alg. 2 steps 5-9 in FP64: the eigenvalues of the sorted tuple are
+// summed left to right, then lam_j is subtracted; if |D|^2 < eps^2 then D = eps.  No
+// fused multiply-add, so every implementation that follows the same order rounds the
+// same way near a resonance.
+__device__ __forceinline__ double2 divisor_fp64(double2 acc, double2 lam_j, double eps)
+{
+#pragma clang fp contract(off)
+    double re = acc.x - lam_j.x;
+    double im = acc.y - lam_j.y;
+    const double mag2 = re * re + im * im;
+    if (mag2 < eps * eps) {
+        re = eps;
+        im = 0.0;
+    }
+    return make_double2(re, im);
+}
+
+__device__ __forceinline__ double2 add_fp64(double2 a, double2 b)
+{
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+
+// (a + ib) / (c + id), plain formula in FP64.
+__device__ __forceinline__ double2 cdiv(double2 a, double2 d)
+{
+    const double den = d.x * d.x + d.y * d.y;
+    return make_double2((a.x * d.x + a.y * d.y) / den, (a.y * d.x - a.x * d.y) / den);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+}  // namespace npf

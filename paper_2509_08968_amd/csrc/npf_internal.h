@@ -1,0 +1,121 @@
+// Internal declarations shared by the planner, the kernels and the C ABI entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "npf.h"
+
+namespace npf {
+
+// Per-thread error message for npf_last_error().
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+// binom(a, b) on the host (exact; 0 outside 0 <= b <= a).
+int64_t binom(int64_t a, int64_t b);
+
+// Workspace layout of a plan.  All offsets are in bytes from the start of `ws` and are
+// multiples of 256.
+struct Layout {
+    int64_t buf[2] = {0, 0};     // ping-pong buffers for the chain T_0 .. T_{M-1}
+    int64_t buf_bytes[2] = {0, 0};
+    int64_t cbuf = 0;            // C / h of one block for the unfused path: [Jpad][U_N] c128
+    int64_t cbuf_bytes = 0;
+    int64_t psum = 0;            // sum of P_M over orders: [n][n] c128
+    int64_t pm = 0;              // P_M of the current order: [n][n] c128
+    int64_t phi = 0;             // contraction-precision copies of Phi (padded)
+    int64_t phi_bytes = 0;
+    int64_t parts = 0;           // per-workgroup partial P of the fused kernel
+    int64_t parts_bytes = 0;
+    int64_t total = 0;
+};
+
+}  // namespace npf
+
+namespace npf {
+// Event pairs recorded around kernel launches when profiling is on.
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        std::string name;
+        hipEvent_t start, stop;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t take();
+    void clear();
+    ~Profiler();
+};
+}  // namespace npf
+
+struct npf_plan_s {
+    npf_problem prob;
+    int64_t n = 0;
+    int N = 0;
+    int prec = NPF_FP64;
+    int64_t U[NPF_MAX_ORDER + 2] = {0};  // U[m] = binom(n + m - 1, m)
+    int64_t J = 0;                       // output modes per block
+    int64_t Jpad = 0;                    // J rounded up to a multiple of 16
+    int64_t n_blocks = 0;
+    int64_t npad = 0;                    // n rounded up to a multiple of 32
+    int64_t esz = 16;                    // bytes per complex element of the chain
+    int64_t n_parts = 0;                 // partial-P slots of the fused kernel
+    npf::Layout lay;
+    npf::Profiler prof;
+};
+
+namespace npf {
+// Brackets one kernel launch with an event pair when the plan is profiling.
+struct Timed {
+    npf_plan_s *plan;
+    std::string name;
+    hipStream_t stream;
+    hipEvent_t start = nullptr;
+    Timed(const npf_plan_s *p, std::string n, hipStream_t s);
+    ~Timed();
+};
+}  // namespace npf
+
+namespace npf {
+
+// Kernel launchers (npf_kernels.hip).  All enqueue on `stream` and return hipError_t.
+struct ChainArgs {
+    const npf_plan_s *plan;
+    int M;                    // order
+    int64_t j0, J;            // block's first mode and its number of modes
+    const npf_tensor *A;
+    const double *U;          // Psi, complex128 interleaved
+    const double *V;          // Phi
+    char *ws;
+    hipStream_t stream;
+};
+
+// G = Psi[j0:j0+J, :] A_M over sorted tuples, into buffer 0 (T_0).
+hipError_t launch_psi_a(const ChainArgs &a);
+// Stage i (1 <= i <= M-1) of the lower-index chain: T_{i-1} -> T_i.
+hipError_t launch_stage(const ChainArgs &a, int i);
+// Last stage, writes C (complex128, [J][U_M], scaled by 1/M!) to C_out.
+hipError_t launch_last_to_c(const ChainArgs &a, double *C_out);
+// h = C / D in place on [J][U_M].
+hipError_t launch_normal_form(const npf_plan_s *p, int M, int64_t j0, int64_t J,
+                              const double *lam, double *C, hipStream_t s);
+// P_acc[j0+jj][k] += -sum_t m(t) h[jj][t] prod zeta_k[t_i]  (deterministic per entry).
+hipError_t launch_assemble(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *h,
+                           const double *U, double *P_acc, hipStream_t s);
+// NPF = Phi o (delta Psi + P_sum)^T.
+hipError_t launch_finalize(const npf_plan_s *p, const double *U, const double *V,
+                           const double *P_sum, double *npf_out, hipStream_t s);
+// Fill `count` doubles with zero.
+hipError_t launch_zero(double *x, int64_t count, hipStream_t s);
+// dst[i] += src[i] (or dst = src when first), count doubles.
+hipError_t launch_accumulate(double *dst, const double *src, int64_t count, bool first,
+                             hipStream_t s);
+// Copy rows [j0, j0+J) of an n x n complex matrix.
+hipError_t launch_copy_rows(double *dst, const double *src, int64_t n, int64_t j0, int64_t J,
+                            hipStream_t s);
+
+}  // namespace npf

@@ -195,11 +195,13 @@ def resonant_system(n: int, orders, seed: int, n_res2: int = 4, n_res3: int = 4,
     sources that are not targets, |eta| log-uniform in [eta_lo, eta_hi] and a uniform
     phase; the conjugate partner follows.  A_M entries are N(0,1) / n^(M/2).
     """
+    n_t = n_res2 + n_res3
+    if n_t + 2 * n_res2 + 3 * n_res3 > n // 2:
+        raise ValueError("not enough conjugate pairs for distinct targets and sources")
     rng = np.random.default_rng(seed)
     while True:
         lam = _spectrum(n, rng)
         pairs = rng.permutation(n // 2)
-        n_t = n_res2 + n_res3
         targets, sources = pairs[:n_t], list(pairs[n_t:])
         cursor = 0
         for idx, m in enumerate(targets):

@@ -1,0 +1,111 @@
+"""Parity of the HIP path with the CPU FP64 oracle, through the C ABI (needs a GPU).
+
+Tolerances (relative Frobenius error per order and per quantity): 1e-10 for the FP64
+path, 1e-6 for the FP32 and split-BF16 paths.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_08968_amd import binding as B
+from paper_2509_08968_amd import inputs as I
+from tests.helpers import PARITY_CASES, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+    return torch, "cuda:0"
+
+
+def _oracle_all(s):
+    ref = {M: oracle.sym(s, M, want_C=True, want_h=True) for M in s.orders}
+    npf = oracle.assemble(s, sum(r["P"] for r in ref.values()))
+    return ref, npf
+
+
+@pytest.mark.parametrize("case", sorted(PARITY_CASES))
+def test_staged_steps_fp64(torch_dev, case):
+    torch, dev = torch_dev
+    s = PARITY_CASES[case]()
+    print(f"[staged fp64] {case}", flush=True)
+    ref, _ = _oracle_all(s)
+    d = B.upload_system(s, dev)
+    plan = B.Plan(s.n, s.order_max, "fp64", s.eps, s.tau, s.delta)
+    ws = plan.workspace(dev)
+    for M in s.orders:
+        UM = plan.unique_tuples[M]
+        C = torch.empty((s.n, UM), dtype=torch.complex128, device=dev)
+        plan.modal_contract(M, B.NPF_ALL_BLOCKS, d.tensors[M - 2], d.U, d.V, ws, C)
+        torch.cuda.synchronize()
+        assert rel(C.cpu().numpy(), ref[M]["C"]) <= TOL["fp64"], "C"
+        plan.normal_form(M, B.NPF_ALL_BLOCKS, d.lam, C)
+        torch.cuda.synchronize()
+        assert rel(C.cpu().numpy(), ref[M]["h"]) <= TOL["fp64"], "h"
+        P = torch.zeros((s.n, s.n), dtype=torch.complex128, device=dev)
+        plan.assemble(M, B.NPF_ALL_BLOCKS, C, d.U, P)
+        torch.cuda.synchronize()
+        assert rel(P.cpu().numpy(), ref[M]["P"]) <= TOL["fp64"], "P"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(PARITY_CASES))
+def test_run_matches_oracle(torch_dev, case, precision):
+    s = PARITY_CASES[case]()
+    print(f"[run {precision}] {case}", flush=True)
+    ref, npf_ref = _oracle_all(s)
+    npf, Ps = B.compute(s, precision)
+    for M in s.orders:
+        assert rel(Ps[M], ref[M]["P"]) <= TOL[precision], f"P_{M}"
+    assert rel(npf, npf_ref) <= TOL[precision], "NPF"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_blocks_over_modes_match_single_block(torch_dev, precision):
+    s = I.dense_system(40, [2, 3], 3201)
+    print(f"[blocks {precision}] n=40", flush=True)
+    one, P1 = B.compute(s, precision)
+    many, P3 = B.compute(s, precision, block_modes=16)
+    for M in s.orders:
+        assert np.array_equal(P1[M], P3[M])
+    assert np.array_equal(one, many)
+    ref, npf_ref = _oracle_all(s)
+    assert rel(many, npf_ref) <= TOL[precision]
+
+
+def test_run_is_deterministic(torch_dev):
+    s = I.block_sparse_system(32, [2, 3], 3301)
+    print("[determinism] n=32", flush=True)
+    a, Pa = B.compute(s, "fp64")
+    b, Pb = B.compute(s, "fp64")
+    assert np.array_equal(a, b)
+    for M in s.orders:
+        assert np.array_equal(Pa[M], Pb[M])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_workload_n64_o3_blocksparse_full(torch_dev, precision):
+    """The benchmarked workload at full size (n=64, orders 2-3, block-sparse)."""
+    s = I.workload_sparse64()
+    print(f"[n64-o3-blocksparse {precision}]", flush=True)
+    ref, npf_ref = _oracle_all(s)
+    npf, Ps = B.compute(s, precision)
+    for M in s.orders:
+        assert rel(Ps[M], ref[M]["P"]) <= TOL[precision], f"P_{M}"
+    assert rel(npf, npf_ref) <= TOL[precision]
+
+
+def test_linear_limit_on_gpu(torch_dev):
+    """A_M = 0: NPF is the linear participation factor delta * Phi o Psi^T exactly."""
+    s = I.dense_system(16, [2, 3], 3401, delta=0.5)
+    for M in s.orders:
+        s.A[M] = np.zeros_like(s.A[M])
+    npf, Ps = B.compute(s, "fp64")
+    assert all(np.abs(P).max() == 0 for P in Ps.values())
+    assert rel(npf, 0.5 * s.V * s.U.T) < 1e-15
