@@ -75,11 +75,21 @@ int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tenso
         Timed t(p, kname(M, "psi_a"), s);
         rc = check_hip(launch_psi_a(a), "upper-index contraction");
     }
+    const bool mfma = stage_mfma_supported(p);
     for (int i = 1; rc == NPF_OK && i < M; ++i) {
         Timed t(p, kname(M, "stage", i), s);
-        rc = check_hip(launch_stage(a, i), "chain stage");
+        rc = check_hip(mfma ? launch_stage_mfma(a, i) : launch_stage(a, i), "chain stage");
     }
     return rc;
+}
+
+int stage_operands(const npf_plan_s *p, const void *U, const void *V, void *ws, hipStream_t s)
+{
+    Timed t(p, "stage_operands", s);
+    return check_hip(launch_stage_operands(p, static_cast<const double *>(U),
+                                           static_cast<const double *>(V),
+                                           static_cast<char *>(ws), s),
+                     "operand staging");
 }
 
 }  // namespace
@@ -97,6 +107,7 @@ extern "C" int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block,
     hipStream_t s = static_cast<hipStream_t>(stream);
     int64_t b0, b1;
     block_range(plan, block, b0, b1);
+    rc = stage_operands(plan, U, V, ws, s);
     for (int64_t b = b0; b < b1 && rc == NPF_OK; ++b) {
         int64_t j0, J;
         block_modes(plan, b, j0, J);
@@ -175,33 +186,24 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
     char *w = static_cast<char *>(ws);
     const int64_t nn = plan->n * plan->n;
     double *psum = reinterpret_cast<double *>(w + plan->lay.psum);
-    double *cbuf = reinterpret_cast<double *>(w + plan->lay.cbuf);
     double *pm = reinterpret_cast<double *>(w + plan->lay.pm);
+    rc = stage_operands(plan, U, V, ws, s);
     for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
         double *PM = P_out ? static_cast<double *>(P_out) + 2 * (M - 2) * nn : pm;
-        rc = check_hip(launch_zero(PM, 2 * nn, s), "zero P");
         for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
             int64_t j0, J;
             block_modes(plan, b, j0, J);
             rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, s);
             if (rc) break;
-            ChainArgs a{plan, M, j0, J, &A[M - 2], static_cast<const double *>(U),
-                        static_cast<const double *>(V), w, s};
             {
-                Timed t(plan, kname(M, "last_to_c"), s);
-                rc = check_hip(launch_last_to_c(a, cbuf), "last contraction stage");
+                Timed t(plan, kname(M, "fused"), s);
+                rc = check_hip(launch_fused_last(plan, M, j0, J,
+                                                 static_cast<const double *>(lambda), w, s),
+                               "fused last stage");
             }
             if (!rc) {
-                Timed t(plan, kname(M, "normal_form"), s);
-                rc = check_hip(launch_normal_form(plan, M, j0, J,
-                                                  static_cast<const double *>(lambda), cbuf, s),
-                               "normal form");
-            }
-            if (!rc) {
-                Timed t(plan, kname(M, "assemble"), s);
-                rc = check_hip(launch_assemble(plan, M, j0, J, cbuf,
-                                               static_cast<const double *>(U), PM, s),
-                               "assemble");
+                Timed t(plan, kname(M, "reduce"), s);
+                rc = check_hip(launch_reduce_parts(plan, M, j0, J, PM, w, s), "partial sums");
             }
         }
         if (!rc) rc = check_hip(launch_accumulate(psum, PM, 2 * nn, M == 2, s), "sum over orders");

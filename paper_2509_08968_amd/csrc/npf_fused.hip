@@ -1,0 +1,519 @@
+// Fused last stage of the chain on MFMA: for every sorted mode prefix p of length M-1,
+//   S[t][j]  = sum_a Phi[a][t] X_p[a][j]                       (last mode product, t >= last(p))
+//   h'[j][t] = S[t][j] W(p,t) / D(j, p U t)                     (divisor in FP64, Alg. 2 steps 5-11)
+//   P[j][k] += zp[k] sum_t h'[j][t] zeta[t][k]                  (Alg. 2 steps 12-19)
+// with X_p = T_{M-1}[p] (all upper-index and M-1 lower-index contractions done),
+// zeta = delta Psi, zp[k] = prod_i zeta[p_i][k], W(p,t) = -1/prod_v c_v! over the value
+// counts of the sorted tuple p U t (the orderings of the tuple times 1/M!), and
+// D = (lam_{p_1} + .. + lam_{p_{M-1}} + lam_t) - lam_j, |D| < eps -> eps.
+// h' never leaves registers: the accumulator layout of the first product is re-used as
+// the A operand of the second.  Each workgroup accumulates its items in FP64 and writes
+// one partial; a second kernel sums the partials in a fixed order (deterministic).
+#include "npf_device.h"
+#include "npf_internal.h"
+#include "npf_mfma.h"
+
+namespace npf {
+
+namespace {
+
+constexpr int kWaves = 4;               // one 16-mode j-tile per wave
+constexpr int kThreads = 64 * kWaves;
+
+// ------------------------------------------------------------------ operand staging
+// zeta64[t][k] = delta Psi[t][k] (FP64, zero padded to npad).  Engine copies:
+//   F64: phi[a][t], zeta[t][k] as double2;  F32: the same as float2;
+//   BF3: phi as 9 BF16 planes (re h/m/l, im h/m/l, -im h/m/l) in layout [pl][a/8][t][a%8],
+//        zeta as 6 planes (re h/m/l, im h/m/l) in layout [pl][t/4][k][t%4].
+__global__ void __launch_bounds__(256)
+stage_operands(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta,
+               int64_t n, int64_t npad, int eng, double2 *__restrict__ zeta64,
+               void *__restrict__ phiE, void *__restrict__ zetaE)
+{
+    const int64_t total = npad * npad;
+    for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+         x += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = x / npad, c = x % npad;   // r = a or t, c = t or k
+        const bool in = r < n && c < n;
+        const double2 ph = in ? Phi[r * n + c] : make_double2(0.0, 0.0);
+        double2 ze = in ? Psi[r * n + c] : make_double2(0.0, 0.0);
+        ze = make_double2(delta * ze.x, delta * ze.y);
+        zeta64[x] = ze;
+        if (eng == int(Eng::F64)) {
+            static_cast<double2 *>(phiE)[x] = ph;
+            static_cast<double2 *>(zetaE)[x] = ze;
+        } else if (eng == int(Eng::F32)) {
+            static_cast<float2 *>(phiE)[x] = make_float2(float(ph.x), float(ph.y));
+            static_cast<float2 *>(zetaE)[x] = make_float2(float(ze.x), float(ze.y));
+        } else {
+            // phi: a = r, t = c
+            __bf16 *P = static_cast<__bf16 *>(phiE);
+            const int64_t plane = npad * npad;
+            const int64_t pidx = ((r / 8) * npad + c) * 8 + (r % 8);
+            __bf16 h, m, l;
+            split3(float(ph.x), h, m, l);
+            P[0 * plane + pidx] = h; P[1 * plane + pidx] = m; P[2 * plane + pidx] = l;
+            split3(float(ph.y), h, m, l);
+            P[3 * plane + pidx] = h; P[4 * plane + pidx] = m; P[5 * plane + pidx] = l;
+            split3(float(-ph.y), h, m, l);
+            P[6 * plane + pidx] = h; P[7 * plane + pidx] = m; P[8 * plane + pidx] = l;
+            // zeta: t = r, k = c
+            __bf16 *Z = static_cast<__bf16 *>(zetaE);
+            const int64_t zidx = ((r / 4) * npad + c) * 4 + (r % 4);
+            split3(float(ze.x), h, m, l);
+            Z[0 * plane + zidx] = h; Z[1 * plane + zidx] = m; Z[2 * plane + zidx] = l;
+            split3(float(ze.y), h, m, l);
+            Z[3 * plane + zidx] = h; Z[4 * plane + zidx] = m; Z[5 * plane + zidx] = l;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ per-item constants
+struct ItemInfo {
+    int32_t m;          // last(p)
+    double2 lam_p;      // lam_{p_1} + .. + lam_{p_{M-1}}, left to right
+    double w_gt, w_eq;  // W(p,t) for t > m and t == m
+};
+
+__device__ void item_info(int64_t rp, int M, int64_t n, const double2 *lam, int32_t *p,
+                          ItemInfo &info)
+{
+    colex_unrank(rp, M - 1, n, p);
+    double2 acc = lam[p[0]];
+    for (int i = 1; i < M - 1; ++i) acc = add_fp64(acc, lam[p[i]]);
+    double den = 1.0;
+    int run = 1;
+    for (int i = 1; i < M - 1; ++i) {
+        if (p[i] == p[i - 1]) {
+            ++run;
+            den *= double(run);
+        } else {
+            run = 1;
+        }
+    }
+    // run = count of the last value m in p.
+    info.m = p[M - 2];
+    info.lam_p = acc;
+    info.w_gt = -1.0 / den;
+    info.w_eq = -1.0 / (den * double(run + 1));
+}
+
+// h' = S W / D for one element; FP64 divisor, FP64 or FP32 division.
+template <Eng E>
+__device__ __forceinline__ void scaled_quotient(typename EngT<E>::real sr, typename EngT<E>::real si,
+                                                double2 d, double w, double tau2,
+                                                typename EngT<E>::real &hr, typename EngT<E>::real &hi)
+{
+    const double den = d.x * d.x + d.y * d.y;
+    if constexpr (E == Eng::F64) {
+        const double f = w / den;
+        hr = (sr * d.x + si * d.y) * f;
+        hi = (si * d.x - sr * d.y) * f;
+    } else {
+        if (den < tau2) {
+            const double f = w / den;
+            hr = float((double(sr) * d.x + double(si) * d.y) * f);
+            hi = float((double(si) * d.x - double(sr) * d.y) * f);
+        } else {
+            const float dx = float(d.x), dy = float(d.y);
+            const float f = float(w) / (dx * dx + dy * dy);
+            hr = (sr * dx + si * dy) * f;
+            hi = (si * dx - sr * dy) * f;
+        }
+    }
+}
+
+struct FusedArgs {
+    const void *X;           // T_{M-1}: [U_{M-1}][n][Jpad] complex
+    const void *phiE;        // staged Phi (engine layout)
+    const void *zetaE;       // staged zeta (engine layout)
+    const double2 *zeta64;   // [npad][npad] delta Psi
+    const double2 *lam;      // [n]
+    double2 *parts;          // [gridDim.x][Jpad][n]
+    int64_t n, npad, Jpad, J, j0, items;
+    int M;
+    double eps, tau2;
+};
+
+// ------------------------------------------------------------------ the fused kernel
+// grid: x = item groups (grid-stride over prefixes), y = 64-mode j-groups, z = k-groups of
+// NKTW 16-state tiles.  Block: 4 waves, wave w owns modes jg*64 + 16w .. +15.
+template <Eng E, int NKTW>
+__global__ void __launch_bounds__(kThreads)
+fused_last(FusedArgs a)
+{
+    using T = EngT<E>;
+    using acc_t = typename T::acc;
+    using real = typename T::real;
+    using cplx = typename T::cplx;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;     // wave's first mode (block-local)
+    const bool wave_on = jw < a.Jpad;
+    const int64_t jl = jw + c;                                   // this lane's mode (block-local)
+    const bool j_ok = wave_on && jl < a.J;
+    const double2 lam_j = j_ok ? a.lam[a.j0 + jl] : make_double2(0.0, 0.0);
+    const int kt0 = blockIdx.z * NKTW;
+    const int nkt = int(a.npad / 16);
+    const int TC = T::TC;
+
+    __shared__ int32_t sp[kMaxOrder];
+    __shared__ ItemInfo sinfo;
+
+    // FP64 accumulators of this lane: P[jw + out_row(r,g)][(kt0+kt)*16 + c].
+    double pacc_r[NKTW][4], pacc_i[NKTW][4];
+#pragma unroll
+    for (int kt = 0; kt < NKTW; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pacc_r[kt][r] = pacc_i[kt][r] = 0.0;
+
+    for (int64_t it = blockIdx.x; it < a.items; it += gridDim.x) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_info(it, a.M, a.n, a.lam, sp, sinfo);
+        __syncthreads();
+        const ItemInfo info = sinfo;
+        if (!wave_on) continue;
+        const cplx *Xp = static_cast<const cplx *>(a.X) + it * a.n * a.Jpad;
+
+        // zp[k] for this lane's k columns (FP64).
+        double zr[NKTW], zi[NKTW];
+#pragma unroll
+        for (int kt = 0; kt < NKTW; ++kt) {
+            const int64_t k = int64_t(kt0 + kt) * 16 + c;
+            double2 z = make_double2(1.0, 0.0);
+            if ((kt0 + kt) < nkt)
+                for (int i = 0; i < a.M - 1; ++i) z = cmul(z, a.zeta64[int64_t(sp[i]) * a.npad + k]);
+            zr[kt] = z.x;
+            zi[kt] = z.y;
+        }
+
+        // Per-item GEMM2 accumulators (FP32 engines; the FP64 engine accumulates directly).
+        acc_t rr[NKTW], ri[NKTW];
+#pragma unroll
+        for (int kt = 0; kt < NKTW; ++kt) rr[kt] = ri[kt] = acc_t{0, 0, 0, 0};
+
+        const int64_t tstart = (info.m / TC) * TC;
+        for (int64_t t0 = tstart; t0 < a.npad; t0 += TC) {
+            // ---------------- GEMM1: S^T[t][j] over a, tiles of 16 t.
+            constexpr int NT1 = (E == Eng::BF3) ? 2 : 1;
+            acc_t sr[NT1], si[NT1];
+#pragma unroll
+            for (int u = 0; u < NT1; ++u) sr[u] = si[u] = acc_t{0, 0, 0, 0};
+            if constexpr (E != Eng::BF3) {
+                const cplx *Ph = static_cast<const cplx *>(a.phiE);
+                for (int64_t a0 = 0; a0 < a.npad; a0 += 4) {
+                    const int64_t ar = a0 + g;
+                    const cplx ph = Ph[ar * a.npad + t0 + c];
+                    cplx x;
+                    if (ar < a.n) x = Xp[ar * a.Jpad + jw + c];
+                    else x = cplx{0, 0};
+                    sr[0] = mfma(ph.x, x.x, sr[0]);
+                    sr[0] = mfma(real(-ph.y), x.y, sr[0]);
+                    si[0] = mfma(ph.x, x.y, si[0]);
+                    si[0] = mfma(ph.y, x.x, si[0]);
+                }
+            } else {
+                const __bf16 *Ph = static_cast<const __bf16 *>(a.phiE);
+                const int64_t plane = a.npad * a.npad;
+                for (int64_t a0 = 0; a0 < a.npad; a0 += 32) {
+                    // B operand: X_p rows a0 + 8g + s at mode jw + c, split in three.
+                    Split3 xr, xi;
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) {
+                        const int64_t ar = a0 + 8 * g + s;
+                        float2 x = make_float2(0.f, 0.f);
+                        if (ar < a.n) x = Xp[ar * a.Jpad + jw + c];
+                        __bf16 h, m, l;
+                        split3(x.x, h, m, l);
+                        xr.h[s] = h; xr.m[s] = m; xr.l[s] = l;
+                        split3(x.y, h, m, l);
+                        xi.h[s] = h; xi.m[s] = m; xi.l[s] = l;
+                    }
+#pragma unroll
+                    for (int u = 0; u < NT1; ++u) {
+                        const int64_t pidx = ((a0 / 8 + g) * a.npad + t0 + 16 * u + c) * 8;
+                        Split3 pr, pi, pn;
+                        pr.h = *reinterpret_cast<const v8bf *>(Ph + 0 * plane + pidx);
+                        pr.m = *reinterpret_cast<const v8bf *>(Ph + 1 * plane + pidx);
+                        pr.l = *reinterpret_cast<const v8bf *>(Ph + 2 * plane + pidx);
+                        pi.h = *reinterpret_cast<const v8bf *>(Ph + 3 * plane + pidx);
+                        pi.m = *reinterpret_cast<const v8bf *>(Ph + 4 * plane + pidx);
+                        pi.l = *reinterpret_cast<const v8bf *>(Ph + 5 * plane + pidx);
+                        pn.h = *reinterpret_cast<const v8bf *>(Ph + 6 * plane + pidx);
+                        pn.m = *reinterpret_cast<const v8bf *>(Ph + 7 * plane + pidx);
+                        pn.l = *reinterpret_cast<const v8bf *>(Ph + 8 * plane + pidx);
+                        sr[u] = mm6(pr, xr, sr[u]);
+                        sr[u] = mm6(pn, xi, sr[u]);
+                        si[u] = mm6(pr, xi, si[u]);
+                        si[u] = mm6(pi, xr, si[u]);
+                    }
+                }
+            }
+
+            // ---------------- divisor, division, weights (per element, FP64 divisor).
+            real hr[NT1][4], hi[NT1][4];
+#pragma unroll
+            for (int u = 0; u < NT1; ++u)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t t = t0 + 16 * u + out_row<E>(r, g);
+                    real vr = 0, vi = 0;
+                    if (j_ok && t >= info.m && t < a.n) {
+                        const double2 acc = add_fp64(info.lam_p, a.lam[t]);
+                        const double2 d = divisor_fp64(acc, lam_j, a.eps);
+                        const double w = (t == info.m) ? info.w_eq : info.w_gt;
+                        scaled_quotient<E>(sr[u][r], si[u][r], d, w, a.tau2, vr, vi);
+                    }
+                    hr[u][r] = vr;
+                    hi[u][r] = vi;
+                }
+
+            // ---------------- GEMM2: R[j][k] += sum_t h'[j][t] zeta[t][k].
+            if constexpr (E == Eng::F64) {
+                const double2 *Z = static_cast<const double2 *>(a.zetaE);
+#pragma unroll
+                for (int kt = 0; kt < NKTW; ++kt) {
+                    if (kt0 + kt >= nkt) continue;
+                    const int64_t k = int64_t(kt0 + kt) * 16 + c;
+                    v4d accr, acci;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        accr[q] = pacc_r[kt][q];
+                        acci[q] = pacc_i[kt][q];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t t = t0 + out_row<E>(r, g);
+                        // B = zeta[t][k] * zp[k]: accumulate the item directly in FP64.
+                        const double2 z = Z[t * a.npad + k];
+                        const double br = z.x * zr[kt] - z.y * zi[kt];
+                        const double bi = z.x * zi[kt] + z.y * zr[kt];
+                        accr = mfma(hr[0][r], br, accr);
+                        accr = mfma(-hi[0][r], bi, accr);
+                        acci = mfma(hr[0][r], bi, acci);
+                        acci = mfma(hi[0][r], br, acci);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        pacc_r[kt][q] = accr[q];
+                        pacc_i[kt][q] = acci[q];
+                    }
+                }
+            } else if constexpr (E == Eng::F32) {
+                const float2 *Z = static_cast<const float2 *>(a.zetaE);
+#pragma unroll
+                for (int kt = 0; kt < NKTW; ++kt) {
+                    if (kt0 + kt >= nkt) continue;
+                    const int64_t k = int64_t(kt0 + kt) * 16 + c;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t t = t0 + out_row<E>(r, g);
+                        const float2 z = Z[t * a.npad + k];
+                        rr[kt] = mfma(hr[0][r], z.x, rr[kt]);
+                        rr[kt] = mfma(-hi[0][r], z.y, rr[kt]);
+                        ri[kt] = mfma(hr[0][r], z.y, ri[kt]);
+                        ri[kt] = mfma(hi[0][r], z.x, ri[kt]);
+                    }
+                }
+            } else {
+                // A operand: slot s < 4 <-> t0 + 4g + s (tile 0), s >= 4 <-> t0 + 16 + 4g + s - 4.
+                Split3 ar_, ai_;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int u = s >> 2, r = s & 3;
+                    __bf16 h, m, l;
+                    split3(hr[u][r], h, m, l);
+                    ar_.h[s] = h; ar_.m[s] = m; ar_.l[s] = l;
+                    split3(hi[u][r], h, m, l);
+                    ai_.h[s] = h; ai_.m[s] = m; ai_.l[s] = l;
+                }
+                const Split3 an_ = neg3(ai_);
+                const __bf16 *Z = static_cast<const __bf16 *>(a.zetaE);
+                const int64_t plane = a.npad * a.npad;
+#pragma unroll
+                for (int kt = 0; kt < NKTW; ++kt) {
+                    if (kt0 + kt >= nkt) continue;
+                    const int64_t k = int64_t(kt0 + kt) * 16 + c;
+                    const int64_t z0 = ((t0 / 4 + g) * a.npad + k) * 4;
+                    const int64_t z1 = (((t0 + 16) / 4 + g) * a.npad + k) * 4;
+                    Split3 zr_, zi_;
+                    auto ld = [&](int pl) {
+                        const v4bf lo = *reinterpret_cast<const v4bf *>(Z + pl * plane + z0);
+                        const v4bf hi4 = *reinterpret_cast<const v4bf *>(Z + pl * plane + z1);
+                        v8bf v;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            v[s] = lo[s];
+                            v[s + 4] = hi4[s];
+                        }
+                        return v;
+                    };
+                    zr_.h = ld(0); zr_.m = ld(1); zr_.l = ld(2);
+                    zi_.h = ld(3); zi_.m = ld(4); zi_.l = ld(5);
+                    rr[kt] = mm6(ar_, zr_, rr[kt]);
+                    rr[kt] = mm6(an_, zi_, rr[kt]);
+                    ri[kt] = mm6(ar_, zi_, ri[kt]);
+                    ri[kt] = mm6(ai_, zr_, ri[kt]);
+                }
+            }
+        }
+        // ---------------- item done: P += zp * R in FP64 (FP32 engines).
+        if constexpr (E != Eng::F64) {
+#pragma unroll
+            for (int kt = 0; kt < NKTW; ++kt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double vr = rr[kt][r], vi = ri[kt][r];
+                    pacc_r[kt][r] += vr * zr[kt] - vi * zi[kt];
+                    pacc_i[kt][r] += vr * zi[kt] + vi * zr[kt];
+                }
+        }
+    }
+    if (!wave_on) return;
+    // ---------------- write this workgroup's partial.
+    double2 *dst = a.parts + int64_t(blockIdx.x) * a.Jpad * a.n;
+#pragma unroll
+    for (int kt = 0; kt < NKTW; ++kt) {
+        const int64_t k = int64_t(kt0 + kt) * 16 + c;
+        if (kt0 + kt >= nkt || k >= a.n) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t j = jw + out_row<E>(r, g);
+            if (j < a.Jpad) dst[j * a.n + k] = make_double2(pacc_r[kt][r], pacc_i[kt][r]);
+        }
+    }
+}
+
+// Partial sums in a fixed order, two levels: level 1 sums runs of 16 partials per element
+// (coalesced over k), level 2 sums the level-1 results into rows [j0, j0+J) of P.
+constexpr int kRun = 16;
+
+__global__ void __launch_bounds__(256)
+reduce_parts_l1(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, int64_t J,
+                int64_t n, double2 *__restrict__ out)
+{
+    const int64_t per = J * n;
+    const int64_t nrun = (nparts + kRun - 1) / kRun;
+    const int64_t total = nrun * per;
+    for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+         x += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t q = x / per, e = x % per;
+        const int64_t j = e / n, k = e % n;
+        double sr = 0.0, si = 0.0;
+        const int64_t b1 = (q + 1) * kRun < nparts ? (q + 1) * kRun : nparts;
+        for (int64_t b = q * kRun; b < b1; ++b) {
+            const double2 v = parts[(b * Jpad + j) * n + k];
+            sr += v.x;
+            si += v.y;
+        }
+        out[x] = make_double2(sr, si);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+reduce_parts_l2(const double2 *__restrict__ l1, int64_t nrun, int64_t J, int64_t n, int64_t j0,
+                double2 *__restrict__ P)
+{
+    const int64_t per = J * n;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < per;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t q = 0; q < nrun; ++q) {
+            const double2 v = l1[q * per + e];
+            sr += v.x;
+            si += v.y;
+        }
+        P[j0 * n + e] = make_double2(sr, si);
+    }
+}
+
+template <Eng E>
+hipError_t launch_fused_eng(const FusedArgs &fa, int nkt, int64_t groups, hipStream_t s)
+{
+    int nktw = nkt <= 8 ? nkt : 8;
+    if (nktw % 2) nktw += 1;
+    const int kgroups = (nkt + nktw - 1) / nktw;
+    const dim3 grid(unsigned(groups), unsigned((fa.Jpad + 63) / 64), unsigned(kgroups));
+    switch (nktw) {
+    case 2: hipLaunchKernelGGL((fused_last<E, 2>), grid, dim3(kThreads), 0, s, fa); break;
+    case 4: hipLaunchKernelGGL((fused_last<E, 4>), grid, dim3(kThreads), 0, s, fa); break;
+    case 6: hipLaunchKernelGGL((fused_last<E, 6>), grid, dim3(kThreads), 0, s, fa); break;
+    default: hipLaunchKernelGGL((fused_last<E, 8>), grid, dim3(kThreads), 0, s, fa); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t fused_groups(const npf_plan_s *p, int M)
+{
+    const int64_t items = p->U[M - 1];
+    const int64_t jgroups = (p->Jpad + 63) / 64;
+    int64_t g = 512 / jgroups;
+    if (g < 1) g = 1;
+    return items < g ? items : g;
+}
+
+hipError_t launch_stage_operands(const npf_plan_s *p, const double *U, const double *V, char *ws,
+                                 hipStream_t s)
+{
+    const int64_t N2 = p->npad * p->npad;
+    char *base = ws + p->lay.phi;
+    const int64_t blocks = (N2 + 255) / 256;
+    hipLaunchKernelGGL(stage_operands, dim3(unsigned(blocks < 4096 ? blocks : 4096)), dim3(256), 0,
+                       s, reinterpret_cast<const double2 *>(V), reinterpret_cast<const double2 *>(U),
+                       p->prob.delta, p->n, p->npad, p->prec,
+                       reinterpret_cast<double2 *>(base), base + 16 * N2, base + 34 * N2);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
+                             char *ws, hipStream_t s)
+{
+    const int64_t N2 = p->npad * p->npad;
+    char *base = ws + p->lay.phi;
+    FusedArgs fa;
+    fa.X = ws + p->lay.buf[(M - 1) % 2];
+    fa.phiE = base + 16 * N2;
+    fa.zetaE = base + 34 * N2;
+    fa.zeta64 = reinterpret_cast<const double2 *>(base);
+    fa.lam = reinterpret_cast<const double2 *>(lam);
+    fa.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
+    fa.n = p->n;
+    fa.npad = p->npad;
+    fa.Jpad = p->Jpad;
+    fa.J = J;
+    fa.j0 = j0;
+    fa.items = p->U[M - 1];
+    fa.M = M;
+    fa.eps = p->prob.eps;
+    fa.tau2 = p->prob.tau * p->prob.tau;
+    const int nkt = int(p->npad / 16);
+    const int64_t groups = fused_groups(p, M);
+    switch (p->prec) {
+    case NPF_FP64: return launch_fused_eng<Eng::F64>(fa, nkt, groups, s);
+    case NPF_FP32: return launch_fused_eng<Eng::F32>(fa, nkt, groups, s);
+    default: return launch_fused_eng<Eng::BF3>(fa, nkt, groups, s);
+    }
+}
+
+hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
+                               char *ws, hipStream_t s)
+{
+    const int64_t nparts = fused_groups(p, M);
+    const int64_t nrun = (nparts + kRun - 1) / kRun;
+    const int64_t per = J * p->n;
+    auto blocks = [](int64_t work) {
+        int64_t b = (work + 255) / 256;
+        return unsigned(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+    };
+    double2 *l1 = reinterpret_cast<double2 *>(ws + p->lay.parts2);
+    hipLaunchKernelGGL(reduce_parts_l1, dim3(blocks(nrun * per)), dim3(256), 0, s,
+                       reinterpret_cast<const double2 *>(ws + p->lay.parts), nparts, p->Jpad, J,
+                       p->n, l1);
+    hipLaunchKernelGGL(reduce_parts_l2, dim3(blocks(per)), dim3(256), 0, s, l1, nrun, J, p->n, j0,
+                       reinterpret_cast<double2 *>(P));
+    return hipGetLastError();
+}
+
+}  // namespace npf

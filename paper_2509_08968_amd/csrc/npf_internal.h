@@ -23,14 +23,14 @@ int64_t binom(int64_t a, int64_t b);
 struct Layout {
     int64_t buf[2] = {0, 0};     // ping-pong buffers for the chain T_0 .. T_{M-1}
     int64_t buf_bytes[2] = {0, 0};
-    int64_t cbuf = 0;            // C / h of one block for the unfused path: [Jpad][U_N] c128
-    int64_t cbuf_bytes = 0;
     int64_t psum = 0;            // sum of P_M over orders: [n][n] c128
     int64_t pm = 0;              // P_M of the current order: [n][n] c128
     int64_t phi = 0;             // contraction-precision copies of Phi (padded)
     int64_t phi_bytes = 0;
     int64_t parts = 0;           // per-workgroup partial P of the fused kernel
     int64_t parts_bytes = 0;
+    int64_t parts2 = 0;          // first-level sums of the partials
+    int64_t parts2_bytes = 0;
     int64_t total = 0;
 };
 
@@ -109,6 +109,19 @@ hipError_t launch_assemble(const npf_plan_s *p, int M, int64_t j0, int64_t J, co
 // NPF = Phi o (delta Psi + P_sum)^T.
 hipError_t launch_finalize(const npf_plan_s *p, const double *U, const double *V,
                            const double *P_sum, double *npf_out, hipStream_t s);
+// Operand copies for the fused kernel (zero padded, in the plan's precision).
+hipError_t launch_stage_operands(const npf_plan_s *p, const double *U, const double *V, char *ws,
+                                 hipStream_t s);
+// Fused last mode product + divisor + division + reduction: per-workgroup partial P.
+hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
+                             char *ws, hipStream_t s);
+// Sum of the partials of launch_fused_last into rows [j0, j0+J) of P (fixed order).
+hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
+                               char *ws, hipStream_t s);
+int64_t fused_groups(const npf_plan_s *p, int M);
+// MFMA version of one chain stage (n <= 256).
+bool stage_mfma_supported(const npf_plan_s *p);
+hipError_t launch_stage_mfma(const ChainArgs &a, int i);
 // Fill `count` doubles with zero.
 hipError_t launch_zero(double *x, int64_t count, hipStream_t s);
 // dst[i] += src[i] (or dst = src when first), count doubles.

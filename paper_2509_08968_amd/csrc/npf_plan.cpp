@@ -50,14 +50,16 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     L.buf_bytes[1] = per[1];
     L.buf[0] = take(per[0]);
     L.buf[1] = take(per[1]);
-    L.cbuf_bytes = Jpad * p.U[p.N] * 16;
-    L.cbuf = take(L.cbuf_bytes);
     L.psum = take(p.n * p.n * 16);
     L.pm = take(p.n * p.n * 16);
     L.phi_bytes = p.npad * p.npad * 16 * 4;
     L.phi = take(L.phi_bytes);
-    L.parts_bytes = p.n_parts * Jpad * p.n * 16;
+    const int64_t jgroups = (Jpad + 63) / 64;
+    const int64_t nparts = std::max<int64_t>(1, 512 / jgroups);
+    L.parts_bytes = nparts * Jpad * p.n * 16;
     L.parts = take(L.parts_bytes);
+    L.parts2_bytes = ((nparts + 15) / 16) * Jpad * p.n * 16;
+    L.parts2 = take(L.parts2_bytes);
     L.total = off;
     return L;
 }

@@ -54,7 +54,7 @@ def test_staged_steps_fp64(torch_dev, case):
         assert rel(P.cpu().numpy(), ref[M]["P"]) <= TOL["fp64"], "P"
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("case", sorted(PARITY_CASES))
 def test_run_matches_oracle(torch_dev, case, precision):
     s = PARITY_CASES[case]()
@@ -66,7 +66,7 @@ def test_run_matches_oracle(torch_dev, case, precision):
     assert rel(npf, npf_ref) <= TOL[precision], "NPF"
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_blocks_over_modes_match_single_block(torch_dev, precision):
     s = I.dense_system(40, [2, 3], 3201)
     print(f"[blocks {precision}] n=40", flush=True)
@@ -89,7 +89,7 @@ def test_run_is_deterministic(torch_dev):
         assert np.array_equal(Pa[M], Pb[M])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_workload_n64_o3_blocksparse_full(torch_dev, precision):
     """The benchmarked workload at full size (n=64, orders 2-3, block-sparse)."""
     s = I.workload_sparse64()
