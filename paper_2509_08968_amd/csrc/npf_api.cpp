@@ -85,10 +85,9 @@ int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tenso
 
 int stage_operands(const npf_plan_s *p, const void *U, const void *V, void *ws, hipStream_t s)
 {
-    Timed t(p, "stage_operands", s);
-    return check_hip(launch_stage_operands(p, static_cast<const double *>(U),
-                                           static_cast<const double *>(V),
-                                           static_cast<char *>(ws), s),
+    Timed t(p, "prepare", s);
+    return check_hip(launch_prepare(p, static_cast<const double *>(U),
+                                    static_cast<const double *>(V), static_cast<char *>(ws), s),
                      "operand staging");
 }
 
@@ -203,10 +202,10 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
             }
             if (!rc) {
                 Timed t(plan, kname(M, "reduce"), s);
-                rc = check_hip(launch_reduce_parts(plan, M, j0, J, PM, w, s), "partial sums");
+                rc = check_hip(launch_reduce_parts(plan, M, j0, J, PM, psum, M == 2, w, s),
+                               "partial sums");
             }
         }
-        if (!rc) rc = check_hip(launch_accumulate(psum, PM, 2 * nn, M == 2, s), "sum over orders");
     }
     if (!rc && npf_out) {
         Timed t(plan, "finalize", s);

@@ -19,6 +19,25 @@ __host__ __device__ __forceinline__ int64_t colex_term(int64_t x, int i)
     return r;
 }
 
+// colex_term with constant divisors for the orders used here (i <= 6), x < 2^16.
+__host__ __device__ __forceinline__ int64_t colex_term_c(int64_t x, int i)
+{
+    switch (i) {
+    case 1: return x;
+    case 2: return x * (x + 1) / 2;
+    case 3: return x * (x + 1) * (x + 2) / 6;
+    case 4: return x * (x + 1) * (x + 2) * (x + 3) / 24;
+    case 5: return x * (x + 1) * (x + 2) * (x + 3) * (x + 4) / 120;
+    default: return colex_term(x, i);
+    }
+}
+
+// Sorted tuples of length <= 7 over n <= 256 states are packed 8 bits per entry.
+__host__ __device__ __forceinline__ void unpack_tuple(uint64_t pk, int m, int32_t *t)
+{
+    for (int i = 0; i < m; ++i) t[i] = int32_t((pk >> (8 * i)) & 0xff);
+}
+
 // Colex rank of a sorted m-tuple.
 __host__ __device__ __forceinline__ int64_t colex_rank(const int32_t *t, int m)
 {
@@ -70,6 +89,59 @@ __host__ __device__ __forceinline__ int64_t colex_rank_insert(int32_t a, const i
     }
     if (!placed) r += colex_term(a, pos);
     return r;
+}
+
+// rank(sort({a} U s)) for a fixed sorted suffix s of length m, with the parts that do not
+// depend on a precomputed: = lo[q] + colex_term(a, q + 1) + hi[q], q = #{l : s_l <= a}.
+struct InsertRank {
+    int m;
+    int32_t s[NPF_MAX_ORDER];
+    int64_t lo[NPF_MAX_ORDER + 1], hi[NPF_MAX_ORDER + 1];
+
+    __host__ __device__ void init(const int32_t *s_, int m_)
+    {
+        m = m_;
+        for (int l = 0; l < m; ++l) s[l] = s_[l];
+        lo[0] = 0;
+        for (int q = 1; q <= m; ++q) lo[q] = lo[q - 1] + colex_term_c(s[q - 1], q);
+        hi[m] = 0;
+        for (int q = m - 1; q >= 0; --q) hi[q] = hi[q + 1] + colex_term_c(s[q], q + 2);
+    }
+    __host__ __device__ int64_t rank(int32_t a) const
+    {
+        int q = 0;
+        for (int l = 0; l < m; ++l) q += (s[l] <= a) ? 1 : 0;
+        return lo[q] + colex_term_c(a, q + 1) + hi[q];
+    }
+};
+
+// rank(sort({a} U s)) with s held in registers (no dynamically indexed arrays).
+__host__ __device__ __forceinline__ int64_t rank_insert_reg(int32_t a,
+                                                            const int32_t (&s)[NPF_MAX_ORDER],
+                                                            int m)
+{
+    int64_t r = 0;
+    int q = 0;
+#pragma unroll
+    for (int l = 0; l < NPF_MAX_ORDER; ++l) {
+        if (l < m) {
+            if (s[l] <= a) {
+                r += colex_term_c(s[l], l + 1);
+                ++q;
+            } else {
+                r += colex_term_c(s[l], l + 2);
+            }
+        }
+    }
+    return r + colex_term_c(a, q + 1);
+}
+
+// unpack_tuple into a fixed-size register array.
+__host__ __device__ __forceinline__ void unpack_tuple_reg(uint64_t pk, int m,
+                                                          int32_t (&t)[NPF_MAX_ORDER])
+{
+#pragma unroll
+    for (int i = 0; i < NPF_MAX_ORDER; ++i) t[i] = (i < m) ? int32_t((pk >> (8 * i)) & 0xff) : 0;
 }
 
 // Orderings of a sorted tuple: M! / prod(count_v!).

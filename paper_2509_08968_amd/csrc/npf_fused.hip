@@ -8,7 +8,7 @@
 // D = (lam_{p_1} + .. + lam_{p_{M-1}} + lam_t) - lam_j, |D| < eps -> eps.
 // h' never leaves registers: the accumulator layout of the first product is re-used as
 // the A operand of the second.  Each workgroup accumulates its items in FP64 and writes
-// one partial; a second kernel sums the partials in a fixed order (deterministic).
+// one partial; two small kernels sum the partials in a fixed order (deterministic).
 #include "npf_device.h"
 #include "npf_internal.h"
 #include "npf_mfma.h"
@@ -19,26 +19,45 @@ namespace {
 
 constexpr int kWaves = 4;               // one 16-mode j-tile per wave
 constexpr int kThreads = 64 * kWaves;
+constexpr int64_t kResidentBytes = 128 * 1024;   // LDS budget for resident operands
 
 // ------------------------------------------------------------------ operand staging
 // zeta64[t][k] = delta Psi[t][k] (FP64, zero padded to npad).  Engine copies:
 //   F64: phi[a][t], zeta[t][k] as double2;  F32: the same as float2;
-//   BF3: phi as 9 BF16 planes (re h/m/l, im h/m/l, -im h/m/l) in layout [pl][a/8][t][a%8],
-//        zeta as 6 planes (re h/m/l, im h/m/l) in layout [pl][t/4][k][t%4].
+//   BF3: phi as 6 BF16 planes (re h/m/l, im h/m/l) in layout [pl][a/8][t][a%8],
+//        zeta as 6 planes (re h/m/l, im h/m/l) in the fragment order of zeta_frag_index.
+// Also the tables of sorted tuples of length 1..N-1 (8 bits per entry), in colex order.
 __global__ void __launch_bounds__(256)
-stage_operands(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta,
-               int64_t n, int64_t npad, int eng, double2 *__restrict__ zeta64,
-               void *__restrict__ phiE, void *__restrict__ zetaE)
+prepare(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta, int64_t n,
+        int64_t npad, int eng, double2 *__restrict__ zeta64, void *__restrict__ phiE,
+        void *__restrict__ zetaE, float2 *__restrict__ zeta32, uint64_t *__restrict__ ttab,
+        TupleTables tt)
 {
-    const int64_t total = npad * npad;
+    const int64_t N2 = npad * npad;
+    const int64_t total = N2 + tt.total;
     for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
          x += int64_t(gridDim.x) * blockDim.x) {
+        if (x >= N2) {
+            int64_t y = x - N2;
+            int m = 1;
+            while (m < tt.maxlen && y >= tt.count[m]) {
+                y -= tt.count[m];
+                ++m;
+            }
+            int32_t t[NPF_MAX_ORDER];
+            colex_unrank(y, m, n, t);
+            uint64_t pk = 0;
+            for (int i = 0; i < m; ++i) pk |= uint64_t(t[i]) << (8 * i);
+            ttab[tt.off[m] + y] = pk;
+            continue;
+        }
         const int64_t r = x / npad, c = x % npad;   // r = a or t, c = t or k
         const bool in = r < n && c < n;
         const double2 ph = in ? Phi[r * n + c] : make_double2(0.0, 0.0);
         double2 ze = in ? Psi[r * n + c] : make_double2(0.0, 0.0);
         ze = make_double2(delta * ze.x, delta * ze.y);
         zeta64[x] = ze;
+        zeta32[x] = make_float2(float(ze.x), float(ze.y));
         if (eng == int(Eng::F64)) {
             static_cast<double2 *>(phiE)[x] = ph;
             static_cast<double2 *>(zetaE)[x] = ze;
@@ -46,56 +65,21 @@ stage_operands(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi,
             static_cast<float2 *>(phiE)[x] = make_float2(float(ph.x), float(ph.y));
             static_cast<float2 *>(zetaE)[x] = make_float2(float(ze.x), float(ze.y));
         } else {
-            // phi: a = r, t = c
             __bf16 *P = static_cast<__bf16 *>(phiE);
-            const int64_t plane = npad * npad;
-            const int64_t pidx = ((r / 8) * npad + c) * 8 + (r % 8);
+            const int64_t pidx = ((r / 8) * npad + c) * 8 + (r % 8);    // a = r, t = c
             __bf16 h, m, l;
             split3(float(ph.x), h, m, l);
-            P[0 * plane + pidx] = h; P[1 * plane + pidx] = m; P[2 * plane + pidx] = l;
+            P[0 * N2 + pidx] = h; P[1 * N2 + pidx] = m; P[2 * N2 + pidx] = l;
             split3(float(ph.y), h, m, l);
-            P[3 * plane + pidx] = h; P[4 * plane + pidx] = m; P[5 * plane + pidx] = l;
-            split3(float(-ph.y), h, m, l);
-            P[6 * plane + pidx] = h; P[7 * plane + pidx] = m; P[8 * plane + pidx] = l;
-            // zeta: t = r, k = c
+            P[3 * N2 + pidx] = h; P[4 * N2 + pidx] = m; P[5 * N2 + pidx] = l;
             __bf16 *Z = static_cast<__bf16 *>(zetaE);
-            const int64_t zidx = ((r / 4) * npad + c) * 4 + (r % 4);
+            const int64_t zidx = zeta_frag_index(r, c, npad);            // t = r, k = c
             split3(float(ze.x), h, m, l);
-            Z[0 * plane + zidx] = h; Z[1 * plane + zidx] = m; Z[2 * plane + zidx] = l;
+            Z[0 * N2 + zidx] = h; Z[1 * N2 + zidx] = m; Z[2 * N2 + zidx] = l;
             split3(float(ze.y), h, m, l);
-            Z[3 * plane + zidx] = h; Z[4 * plane + zidx] = m; Z[5 * plane + zidx] = l;
+            Z[3 * N2 + zidx] = h; Z[4 * N2 + zidx] = m; Z[5 * N2 + zidx] = l;
         }
     }
-}
-
-// ------------------------------------------------------------------ per-item constants
-struct ItemInfo {
-    int32_t m;          // last(p)
-    double2 lam_p;      // lam_{p_1} + .. + lam_{p_{M-1}}, left to right
-    double w_gt, w_eq;  // W(p,t) for t > m and t == m
-};
-
-__device__ void item_info(int64_t rp, int M, int64_t n, const double2 *lam, int32_t *p,
-                          ItemInfo &info)
-{
-    colex_unrank(rp, M - 1, n, p);
-    double2 acc = lam[p[0]];
-    for (int i = 1; i < M - 1; ++i) acc = add_fp64(acc, lam[p[i]]);
-    double den = 1.0;
-    int run = 1;
-    for (int i = 1; i < M - 1; ++i) {
-        if (p[i] == p[i - 1]) {
-            ++run;
-            den *= double(run);
-        } else {
-            run = 1;
-        }
-    }
-    // run = count of the last value m in p.
-    info.m = p[M - 2];
-    info.lam_p = acc;
-    info.w_gt = -1.0 / den;
-    info.w_eq = -1.0 / (den * double(run + 1));
 }
 
 // h' = S W / D for one element; FP64 divisor, FP64 or FP32 division.
@@ -129,16 +113,23 @@ struct FusedArgs {
     const void *zetaE;       // staged zeta (engine layout)
     const double2 *zeta64;   // [npad][npad] delta Psi
     const double2 *lam;      // [n]
+    const uint64_t *ptab;    // sorted (M-1)-tuples, packed
     double2 *parts;          // [gridDim.x][Jpad][n]
     int64_t n, npad, Jpad, J, j0, items;
     int M;
     double eps, tau2;
 };
 
+template <Eng E> constexpr int64_t resident_bytes(int64_t npad)
+{
+    return (E == Eng::F64 ? 32 : (E == Eng::F32 ? 16 : 24)) * npad * npad;
+}
+
 // ------------------------------------------------------------------ the fused kernel
 // grid: x = item groups (grid-stride over prefixes), y = 64-mode j-groups, z = k-groups of
-// NKTW 16-state tiles.  Block: 4 waves, wave w owns modes jg*64 + 16w .. +15.
-template <Eng E, int NKTW>
+// NKTW 16-state tiles.  Block: 4 waves, wave w owns modes jg*64 + 16w .. +15.  With RES the
+// Phi and zeta operands are copied to LDS once and every fragment is read from there.
+template <Eng E, int NKTW, bool RES>
 __global__ void __launch_bounds__(kThreads)
 fused_last(FusedArgs a)
 {
@@ -146,6 +137,7 @@ fused_last(FusedArgs a)
     using acc_t = typename T::acc;
     using real = typename T::real;
     using cplx = typename T::cplx;
+    extern __shared__ __align__(16) char lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;     // wave's first mode (block-local)
@@ -155,10 +147,26 @@ fused_last(FusedArgs a)
     const double2 lam_j = j_ok ? a.lam[a.j0 + jl] : make_double2(0.0, 0.0);
     const int kt0 = blockIdx.z * NKTW;
     const int nkt = int(a.npad / 16);
-    const int TC = T::TC;
+    constexpr int TC = T::TC;
+    const int64_t N2 = a.npad * a.npad;
 
-    __shared__ int32_t sp[kMaxOrder];
-    __shared__ ItemInfo sinfo;
+    // Operand bases: LDS copies (RES) or the staged global copies.
+    const char *phiB = static_cast<const char *>(a.phiE);
+    const char *zetaB = static_cast<const char *>(a.zetaE);
+    if constexpr (RES) {
+        const int64_t half = resident_bytes<E>(a.npad) / 2;
+        const int4 *gp = reinterpret_cast<const int4 *>(a.phiE);
+        const int4 *gz = reinterpret_cast<const int4 *>(a.zetaE);
+        int4 *lp = reinterpret_cast<int4 *>(lds);
+        int4 *lz = reinterpret_cast<int4 *>(lds + half);
+        for (int64_t x = threadIdx.x; x < half / 16; x += blockDim.x) {
+            lp[x] = gp[x];
+            lz[x] = gz[x];
+        }
+        __syncthreads();
+        phiB = lds;
+        zetaB = lds + half;
+    }
 
     // FP64 accumulators of this lane: P[jw + out_row(r,g)][(kt0+kt)*16 + c].
     double pacc_r[NKTW][4], pacc_i[NKTW][4];
@@ -167,12 +175,25 @@ fused_last(FusedArgs a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) pacc_r[kt][r] = pacc_i[kt][r] = 0.0;
 
+    if (wave_on)
     for (int64_t it = blockIdx.x; it < a.items; it += gridDim.x) {
-        __syncthreads();
-        if (threadIdx.x == 0) item_info(it, a.M, a.n, a.lam, sp, sinfo);
-        __syncthreads();
-        const ItemInfo info = sinfo;
-        if (!wave_on) continue;
+        // ---------------- item constants (uniform): p, last(p), lam sum, weights.
+        int32_t p[NPF_MAX_ORDER];
+        unpack_tuple(a.ptab[it], a.M - 1, p);
+        double2 lam_p = a.lam[p[0]];
+        double den = 1.0;
+        int run = 1;
+        for (int i = 1; i < a.M - 1; ++i) {
+            lam_p = add_fp64(lam_p, a.lam[p[i]]);
+            if (p[i] == p[i - 1]) {
+                ++run;
+                den *= double(run);
+            } else {
+                run = 1;
+            }
+        }
+        const int m = p[a.M - 2];
+        const double w_gt = -1.0 / den, w_eq = -1.0 / (den * double(run + 1));
         const cplx *Xp = static_cast<const cplx *>(a.X) + it * a.n * a.Jpad;
 
         // zp[k] for this lane's k columns (FP64).
@@ -182,7 +203,7 @@ fused_last(FusedArgs a)
             const int64_t k = int64_t(kt0 + kt) * 16 + c;
             double2 z = make_double2(1.0, 0.0);
             if ((kt0 + kt) < nkt)
-                for (int i = 0; i < a.M - 1; ++i) z = cmul(z, a.zeta64[int64_t(sp[i]) * a.npad + k]);
+                for (int i = 0; i < a.M - 1; ++i) z = cmul(z, a.zeta64[int64_t(p[i]) * a.npad + k]);
             zr[kt] = z.x;
             zi[kt] = z.y;
         }
@@ -192,15 +213,14 @@ fused_last(FusedArgs a)
 #pragma unroll
         for (int kt = 0; kt < NKTW; ++kt) rr[kt] = ri[kt] = acc_t{0, 0, 0, 0};
 
-        const int64_t tstart = (info.m / TC) * TC;
-        for (int64_t t0 = tstart; t0 < a.npad; t0 += TC) {
+        for (int64_t t0 = (m / TC) * TC; t0 < a.npad; t0 += TC) {
             // ---------------- GEMM1: S^T[t][j] over a, tiles of 16 t.
             constexpr int NT1 = (E == Eng::BF3) ? 2 : 1;
             acc_t sr[NT1], si[NT1];
 #pragma unroll
             for (int u = 0; u < NT1; ++u) sr[u] = si[u] = acc_t{0, 0, 0, 0};
             if constexpr (E != Eng::BF3) {
-                const cplx *Ph = static_cast<const cplx *>(a.phiE);
+                const cplx *Ph = reinterpret_cast<const cplx *>(phiB);
                 for (int64_t a0 = 0; a0 < a.npad; a0 += 4) {
                     const int64_t ar = a0 + g;
                     const cplx ph = Ph[ar * a.npad + t0 + c];
@@ -213,8 +233,7 @@ fused_last(FusedArgs a)
                     si[0] = mfma(ph.y, x.x, si[0]);
                 }
             } else {
-                const __bf16 *Ph = static_cast<const __bf16 *>(a.phiE);
-                const int64_t plane = a.npad * a.npad;
+                const __bf16 *Ph = reinterpret_cast<const __bf16 *>(phiB);
                 for (int64_t a0 = 0; a0 < a.npad; a0 += 32) {
                     // B operand: X_p rows a0 + 8g + s at mode jw + c, split in three.
                     Split3 xr, xi;
@@ -223,25 +242,23 @@ fused_last(FusedArgs a)
                         const int64_t ar = a0 + 8 * g + s;
                         float2 x = make_float2(0.f, 0.f);
                         if (ar < a.n) x = Xp[ar * a.Jpad + jw + c];
-                        __bf16 h, m, l;
-                        split3(x.x, h, m, l);
-                        xr.h[s] = h; xr.m[s] = m; xr.l[s] = l;
-                        split3(x.y, h, m, l);
-                        xi.h[s] = h; xi.m[s] = m; xi.l[s] = l;
+                        __bf16 h, mm, l;
+                        split3(x.x, h, mm, l);
+                        xr.h[s] = h; xr.m[s] = mm; xr.l[s] = l;
+                        split3(x.y, h, mm, l);
+                        xi.h[s] = h; xi.m[s] = mm; xi.l[s] = l;
                     }
 #pragma unroll
                     for (int u = 0; u < NT1; ++u) {
                         const int64_t pidx = ((a0 / 8 + g) * a.npad + t0 + 16 * u + c) * 8;
-                        Split3 pr, pi, pn;
-                        pr.h = *reinterpret_cast<const v8bf *>(Ph + 0 * plane + pidx);
-                        pr.m = *reinterpret_cast<const v8bf *>(Ph + 1 * plane + pidx);
-                        pr.l = *reinterpret_cast<const v8bf *>(Ph + 2 * plane + pidx);
-                        pi.h = *reinterpret_cast<const v8bf *>(Ph + 3 * plane + pidx);
-                        pi.m = *reinterpret_cast<const v8bf *>(Ph + 4 * plane + pidx);
-                        pi.l = *reinterpret_cast<const v8bf *>(Ph + 5 * plane + pidx);
-                        pn.h = *reinterpret_cast<const v8bf *>(Ph + 6 * plane + pidx);
-                        pn.m = *reinterpret_cast<const v8bf *>(Ph + 7 * plane + pidx);
-                        pn.l = *reinterpret_cast<const v8bf *>(Ph + 8 * plane + pidx);
+                        Split3 pr, pi;
+                        pr.h = *reinterpret_cast<const v8bf *>(Ph + 0 * N2 + pidx);
+                        pr.m = *reinterpret_cast<const v8bf *>(Ph + 1 * N2 + pidx);
+                        pr.l = *reinterpret_cast<const v8bf *>(Ph + 2 * N2 + pidx);
+                        pi.h = *reinterpret_cast<const v8bf *>(Ph + 3 * N2 + pidx);
+                        pi.m = *reinterpret_cast<const v8bf *>(Ph + 4 * N2 + pidx);
+                        pi.l = *reinterpret_cast<const v8bf *>(Ph + 5 * N2 + pidx);
+                        const Split3 pn = neg3(pi);
                         sr[u] = mm6(pr, xr, sr[u]);
                         sr[u] = mm6(pn, xi, sr[u]);
                         si[u] = mm6(pr, xi, si[u]);
@@ -258,10 +275,10 @@ fused_last(FusedArgs a)
                 for (int r = 0; r < 4; ++r) {
                     const int64_t t = t0 + 16 * u + out_row<E>(r, g);
                     real vr = 0, vi = 0;
-                    if (j_ok && t >= info.m && t < a.n) {
-                        const double2 acc = add_fp64(info.lam_p, a.lam[t]);
+                    if (j_ok && t >= m && t < a.n) {
+                        const double2 acc = add_fp64(lam_p, a.lam[t]);
                         const double2 d = divisor_fp64(acc, lam_j, a.eps);
-                        const double w = (t == info.m) ? info.w_eq : info.w_gt;
+                        const double w = (t == m) ? w_eq : w_gt;
                         scaled_quotient<E>(sr[u][r], si[u][r], d, w, a.tau2, vr, vi);
                     }
                     hr[u][r] = vr;
@@ -270,7 +287,7 @@ fused_last(FusedArgs a)
 
             // ---------------- GEMM2: R[j][k] += sum_t h'[j][t] zeta[t][k].
             if constexpr (E == Eng::F64) {
-                const double2 *Z = static_cast<const double2 *>(a.zetaE);
+                const double2 *Z = reinterpret_cast<const double2 *>(zetaB);
 #pragma unroll
                 for (int kt = 0; kt < NKTW; ++kt) {
                     if (kt0 + kt >= nkt) continue;
@@ -284,7 +301,7 @@ fused_last(FusedArgs a)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int64_t t = t0 + out_row<E>(r, g);
-                        // B = zeta[t][k] * zp[k]: accumulate the item directly in FP64.
+                        // B = zeta[t][k] * zp[k]: the item is accumulated directly in FP64.
                         const double2 z = Z[t * a.npad + k];
                         const double br = z.x * zr[kt] - z.y * zi[kt];
                         const double bi = z.x * zi[kt] + z.y * zr[kt];
@@ -300,7 +317,7 @@ fused_last(FusedArgs a)
                     }
                 }
             } else if constexpr (E == Eng::F32) {
-                const float2 *Z = static_cast<const float2 *>(a.zetaE);
+                const float2 *Z = reinterpret_cast<const float2 *>(zetaB);
 #pragma unroll
                 for (int kt = 0; kt < NKTW; ++kt) {
                     if (kt0 + kt >= nkt) continue;
@@ -321,33 +338,21 @@ fused_last(FusedArgs a)
 #pragma unroll
                 for (int s = 0; s < 8; ++s) {
                     const int u = s >> 2, r = s & 3;
-                    __bf16 h, m, l;
-                    split3(hr[u][r], h, m, l);
-                    ar_.h[s] = h; ar_.m[s] = m; ar_.l[s] = l;
-                    split3(hi[u][r], h, m, l);
-                    ai_.h[s] = h; ai_.m[s] = m; ai_.l[s] = l;
+                    __bf16 h, mm, l;
+                    split3(hr[u][r], h, mm, l);
+                    ar_.h[s] = h; ar_.m[s] = mm; ar_.l[s] = l;
+                    split3(hi[u][r], h, mm, l);
+                    ai_.h[s] = h; ai_.m[s] = mm; ai_.l[s] = l;
                 }
                 const Split3 an_ = neg3(ai_);
-                const __bf16 *Z = static_cast<const __bf16 *>(a.zetaE);
-                const int64_t plane = a.npad * a.npad;
+                const __bf16 *Z = reinterpret_cast<const __bf16 *>(zetaB);
 #pragma unroll
                 for (int kt = 0; kt < NKTW; ++kt) {
                     if (kt0 + kt >= nkt) continue;
                     const int64_t k = int64_t(kt0 + kt) * 16 + c;
-                    const int64_t z0 = ((t0 / 4 + g) * a.npad + k) * 4;
-                    const int64_t z1 = (((t0 + 16) / 4 + g) * a.npad + k) * 4;
+                    const int64_t z0 = zeta_frag_index(t0 + 4 * g, k, a.npad);
+                    auto ld = [&](int pl) { return *reinterpret_cast<const v8bf *>(Z + pl * N2 + z0); };
                     Split3 zr_, zi_;
-                    auto ld = [&](int pl) {
-                        const v4bf lo = *reinterpret_cast<const v4bf *>(Z + pl * plane + z0);
-                        const v4bf hi4 = *reinterpret_cast<const v4bf *>(Z + pl * plane + z1);
-                        v8bf v;
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            v[s] = lo[s];
-                            v[s + 4] = hi4[s];
-                        }
-                        return v;
-                    };
                     zr_.h = ld(0); zr_.m = ld(1); zr_.l = ld(2);
                     zi_.h = ld(3); zi_.m = ld(4); zi_.l = ld(5);
                     rr[kt] = mm6(ar_, zr_, rr[kt]);
@@ -385,7 +390,8 @@ fused_last(FusedArgs a)
 }
 
 // Partial sums in a fixed order, two levels: level 1 sums runs of 16 partials per element
-// (coalesced over k), level 2 sums the level-1 results into rows [j0, j0+J) of P.
+// (coalesced over k), level 2 sums the level-1 results into rows [j0, j0+J) of P_M and
+// adds P_M into the running sum over orders.
 constexpr int kRun = 16;
 
 __global__ void __launch_bounds__(256)
@@ -412,7 +418,7 @@ reduce_parts_l1(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad,
 
 __global__ void __launch_bounds__(256)
 reduce_parts_l2(const double2 *__restrict__ l1, int64_t nrun, int64_t J, int64_t n, int64_t j0,
-                double2 *__restrict__ P)
+                double2 *__restrict__ P, double2 *__restrict__ psum, int first)
 {
     const int64_t per = J * n;
     for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < per;
@@ -424,7 +430,27 @@ reduce_parts_l2(const double2 *__restrict__ l1, int64_t nrun, int64_t J, int64_t
             si += v.y;
         }
         P[j0 * n + e] = make_double2(sr, si);
+        if (first) {
+            psum[j0 * n + e] = make_double2(sr, si);
+        } else {
+            const double2 o = psum[j0 * n + e];
+            psum[j0 * n + e] = make_double2(o.x + sr, o.y + si);
+        }
     }
+}
+
+template <Eng E, int NKTW, bool RES>
+void launch_one(const dim3 &grid, size_t shm, const FusedArgs &fa, hipStream_t s)
+{
+    if (RES) {
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&fused_last<E, NKTW, RES>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(kResidentBytes));
+            attr = true;
+        }
+    }
+    hipLaunchKernelGGL((fused_last<E, NKTW, RES>), grid, dim3(kThreads), shm, s, fa);
 }
 
 template <Eng E>
@@ -433,12 +459,18 @@ hipError_t launch_fused_eng(const FusedArgs &fa, int nkt, int64_t groups, hipStr
     int nktw = nkt <= 8 ? nkt : 8;
     if (nktw % 2) nktw += 1;
     const int kgroups = (nkt + nktw - 1) / nktw;
-    const dim3 grid(unsigned(groups), unsigned((fa.Jpad + 63) / 64), unsigned(kgroups));
+    const dim3 grid{unsigned(groups), unsigned((fa.Jpad + 63) / 64), unsigned(kgroups)};
+    const int64_t rb = resident_bytes<E>(fa.npad);
+    if (rb <= kResidentBytes && nktw <= 4) {
+        if (nktw == 2) launch_one<E, 2, true>(grid, size_t(rb), fa, s);
+        else launch_one<E, 4, true>(grid, size_t(rb), fa, s);
+        return hipGetLastError();
+    }
     switch (nktw) {
-    case 2: hipLaunchKernelGGL((fused_last<E, 2>), grid, dim3(kThreads), 0, s, fa); break;
-    case 4: hipLaunchKernelGGL((fused_last<E, 4>), grid, dim3(kThreads), 0, s, fa); break;
-    case 6: hipLaunchKernelGGL((fused_last<E, 6>), grid, dim3(kThreads), 0, s, fa); break;
-    default: hipLaunchKernelGGL((fused_last<E, 8>), grid, dim3(kThreads), 0, s, fa); break;
+    case 2: launch_one<E, 2, false>(grid, 0, fa, s); break;
+    case 4: launch_one<E, 4, false>(grid, 0, fa, s); break;
+    case 6: launch_one<E, 6, false>(grid, 0, fa, s); break;
+    default: launch_one<E, 8, false>(grid, 0, fa, s); break;
     }
     return hipGetLastError();
 }
@@ -454,16 +486,19 @@ int64_t fused_groups(const npf_plan_s *p, int M)
     return items < g ? items : g;
 }
 
-hipError_t launch_stage_operands(const npf_plan_s *p, const double *U, const double *V, char *ws,
-                                 hipStream_t s)
+hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V, char *ws,
+                          hipStream_t s)
 {
     const int64_t N2 = p->npad * p->npad;
     char *base = ws + p->lay.phi;
-    const int64_t blocks = (N2 + 255) / 256;
-    hipLaunchKernelGGL(stage_operands, dim3(unsigned(blocks < 4096 ? blocks : 4096)), dim3(256), 0,
-                       s, reinterpret_cast<const double2 *>(V), reinterpret_cast<const double2 *>(U),
-                       p->prob.delta, p->n, p->npad, p->prec,
-                       reinterpret_cast<double2 *>(base), base + 16 * N2, base + 34 * N2);
+    const int64_t work = N2 + p->tt.total;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(prepare, dim3(unsigned(blocks)), dim3(256), 0, s,
+                       reinterpret_cast<const double2 *>(V), reinterpret_cast<const double2 *>(U),
+                       p->prob.delta, p->n, p->npad, p->prec, reinterpret_cast<double2 *>(base),
+                       base + 16 * N2, base + 34 * N2, reinterpret_cast<float2 *>(base + 50 * N2),
+                       reinterpret_cast<uint64_t *>(ws + p->lay.ttab), p->tt);
     return hipGetLastError();
 }
 
@@ -478,6 +513,7 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
     fa.zetaE = base + 34 * N2;
     fa.zeta64 = reinterpret_cast<const double2 *>(base);
     fa.lam = reinterpret_cast<const double2 *>(lam);
+    fa.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
     fa.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
     fa.n = p->n;
     fa.npad = p->npad;
@@ -490,6 +526,7 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
     fa.tau2 = p->prob.tau * p->prob.tau;
     const int nkt = int(p->npad / 16);
     const int64_t groups = fused_groups(p, M);
+    if (bf3_small_supported(p)) return launch_fused_bf3(p, M, j0, J, lam, ws, groups, s);
     switch (p->prec) {
     case NPF_FP64: return launch_fused_eng<Eng::F64>(fa, nkt, groups, s);
     case NPF_FP32: return launch_fused_eng<Eng::F32>(fa, nkt, groups, s);
@@ -498,7 +535,7 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
 }
 
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
-                               char *ws, hipStream_t s)
+                               double *psum, bool first, char *ws, hipStream_t s)
 {
     const int64_t nparts = fused_groups(p, M);
     const int64_t nrun = (nparts + kRun - 1) / kRun;
@@ -512,7 +549,8 @@ hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J
                        reinterpret_cast<const double2 *>(ws + p->lay.parts), nparts, p->Jpad, J,
                        p->n, l1);
     hipLaunchKernelGGL(reduce_parts_l2, dim3(blocks(per)), dim3(256), 0, s, l1, nrun, J, p->n, j0,
-                       reinterpret_cast<double2 *>(P));
+                       reinterpret_cast<double2 *>(P), reinterpret_cast<double2 *>(psum),
+                       first ? 1 : 0);
     return hipGetLastError();
 }
 

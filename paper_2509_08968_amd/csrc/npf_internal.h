@@ -18,6 +18,15 @@ int fail(int code, const std::string &msg);
 // binom(a, b) on the host (exact; 0 outside 0 <= b <= a).
 int64_t binom(int64_t a, int64_t b);
 
+// Tables of sorted tuples of length 1..maxlen (packed 8 bits per entry), in colex order:
+// the tuple of rank r and length m is entry off[m] + r.
+struct TupleTables {
+    int64_t count[NPF_MAX_ORDER + 1] = {0};
+    int64_t off[NPF_MAX_ORDER + 1] = {0};
+    int64_t total = 0;
+    int maxlen = 0;
+};
+
 // Workspace layout of a plan.  All offsets are in bytes from the start of `ws` and are
 // multiples of 256.
 struct Layout {
@@ -25,6 +34,7 @@ struct Layout {
     int64_t buf_bytes[2] = {0, 0};
     int64_t psum = 0;            // sum of P_M over orders: [n][n] c128
     int64_t pm = 0;              // P_M of the current order: [n][n] c128
+    int64_t ttab = 0;            // tuple tables
     int64_t phi = 0;             // contraction-precision copies of Phi (padded)
     int64_t phi_bytes = 0;
     int64_t parts = 0;           // per-workgroup partial P of the fused kernel
@@ -63,7 +73,7 @@ struct npf_plan_s {
     int64_t n_blocks = 0;
     int64_t npad = 0;                    // n rounded up to a multiple of 32
     int64_t esz = 16;                    // bytes per complex element of the chain
-    int64_t n_parts = 0;                 // partial-P slots of the fused kernel
+    npf::TupleTables tt;
     npf::Layout lay;
     npf::Profiler prof;
 };
@@ -109,16 +119,23 @@ hipError_t launch_assemble(const npf_plan_s *p, int M, int64_t j0, int64_t J, co
 // NPF = Phi o (delta Psi + P_sum)^T.
 hipError_t launch_finalize(const npf_plan_s *p, const double *U, const double *V,
                            const double *P_sum, double *npf_out, hipStream_t s);
-// Operand copies for the fused kernel (zero padded, in the plan's precision).
-hipError_t launch_stage_operands(const npf_plan_s *p, const double *U, const double *V, char *ws,
-                                 hipStream_t s);
+// Operand copies for the MFMA kernels (zero padded, in the plan's precision) and the
+// tuple tables.
+hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V, char *ws,
+                          hipStream_t s);
 // Fused last mode product + divisor + division + reduction: per-workgroup partial P.
 hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
                              char *ws, hipStream_t s);
-// Sum of the partials of launch_fused_last into rows [j0, j0+J) of P (fixed order).
+// Sum of the partials of launch_fused_last into rows [j0, j0+J) of P (fixed order), and
+// psum = P (first order) or psum += P.
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
-                               char *ws, hipStream_t s);
+                               double *psum, bool first, char *ws, hipStream_t s);
 int64_t fused_groups(const npf_plan_s *p, int M);
+// Split-BF16 kernels with LDS-resident operands for npad <= 64.
+bool bf3_small_supported(const npf_plan_s *p);
+hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
+                            char *ws, int64_t groups, hipStream_t s);
+hipError_t launch_stage_bf3(const ChainArgs &a, int i);
 // MFMA version of one chain stage (n <= 256).
 bool stage_mfma_supported(const npf_plan_s *p);
 hipError_t launch_stage_mfma(const ChainArgs &a, int i);

@@ -49,16 +49,18 @@ psi_a_dense(const double *__restrict__ A, const double2 *__restrict__ Psi, int64
     }
 }
 
+
+// Sparse source, compressed by sorted tuple: T_0 row r is nonzero only if r is one of the
+// listed tuples.  The rows are cleared by fill_zero first; this kernel writes the listed
+// rows (one thread per listed tuple and mode).
 template <typename C>
 __global__ void __launch_bounds__(kThreads) fill_zero(C *__restrict__ out, int64_t count)
 {
     for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < count;
-         x += int64_t(gridDim.x) * blockDim.x) {
+         x += int64_t(gridDim.x) * blockDim.x)
         out[x] = from_d2<C>(make_double2(0.0, 0.0));
-    }
 }
 
-// Sparse source, compressed by sorted tuple: only the listed tuples of T_0 are nonzero.
 template <typename C, typename Acc>
 __global__ void __launch_bounds__(kThreads)
 psi_a_sparse(const double *__restrict__ vals, const int64_t *__restrict__ col_rank,
@@ -250,20 +252,23 @@ hipError_t launch_psi_a(const ChainArgs &a)
                                dim3(kThreads), 0, a.stream, a.A->values, Psi, p.n, UM, a.j0, a.J,
                                p.Jpad, reinterpret_cast<float2 *>(dst));
     } else {
+        const int64_t total = a.A->ncols * p.Jpad;
         if (p.prec == NPF_FP64) {
             hipLaunchKernelGGL((fill_zero<double2>), dim3(grid_for(UM * p.Jpad)), dim3(kThreads),
                                0, a.stream, reinterpret_cast<double2 *>(dst), UM * p.Jpad);
-            hipLaunchKernelGGL((psi_a_sparse<double2, double>),
-                               dim3(grid_for(a.A->ncols * p.Jpad)), dim3(kThreads), 0, a.stream,
-                               a.A->values, a.A->col_rank, a.A->col_ptr, a.A->row_k, a.A->ncols,
-                               Psi, p.n, a.j0, a.J, p.Jpad, reinterpret_cast<double2 *>(dst));
+            if (total > 0)
+                hipLaunchKernelGGL((psi_a_sparse<double2, double>), dim3(grid_for(total)),
+                                   dim3(kThreads), 0, a.stream, a.A->values, a.A->col_rank,
+                                   a.A->col_ptr, a.A->row_k, a.A->ncols, Psi, p.n, a.j0, a.J,
+                                   p.Jpad, reinterpret_cast<double2 *>(dst));
         } else {
             hipLaunchKernelGGL((fill_zero<float2>), dim3(grid_for(UM * p.Jpad)), dim3(kThreads),
                                0, a.stream, reinterpret_cast<float2 *>(dst), UM * p.Jpad);
-            hipLaunchKernelGGL((psi_a_sparse<float2, float>), dim3(grid_for(a.A->ncols * p.Jpad)),
-                               dim3(kThreads), 0, a.stream, a.A->values, a.A->col_rank,
-                               a.A->col_ptr, a.A->row_k, a.A->ncols, Psi, p.n, a.j0, a.J, p.Jpad,
-                               reinterpret_cast<float2 *>(dst));
+            if (total > 0)
+                hipLaunchKernelGGL((psi_a_sparse<float2, float>), dim3(grid_for(total)),
+                                   dim3(kThreads), 0, a.stream, a.A->values, a.A->col_rank,
+                                   a.A->col_ptr, a.A->row_k, a.A->ncols, Psi, p.n, a.j0, a.J,
+                                   p.Jpad, reinterpret_cast<float2 *>(dst));
         }
     }
     return hipGetLastError();

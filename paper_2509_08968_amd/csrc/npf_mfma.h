@@ -90,6 +90,60 @@ __device__ __forceinline__ v4f mm6(const Split3 &a, const Split3 &b, v4f c)
     return c;
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Position of zeta[t][k] in a BF16 plane laid out so that the reduction's B fragment of
+// lane (g, c) for the 32-row chunk t0 -- rows t0 + 4g + s (s < 4) and t0 + 16 + 4g + s - 4
+// (s >= 4), the K-slot order implied by the first product's accumulator layout -- is one
+// contiguous 16-byte vector.
+__host__ __device__ __forceinline__ int64_t zeta_frag_index(int64_t t, int64_t k, int64_t npad)
+{
+    const int64_t chunk = t >> 5, tt = t & 31;
+    const int64_t g = (tt & 15) >> 2, s = (tt & 3) + ((tt >> 4) << 2);
+    return ((chunk * 4 + g) * npad + k) * 8 + s;
+}
+
+// Exact three-term split by truncation: hi = the top 8 significand bits of x, mid = the top
+// 8 of the remainder, lo = the rest (at most 8 bits), so x = hi + mid + lo exactly for a
+// normal FP32 x.  Two values are split and packed at once (x0 in the low half).
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned &h, unsigned &m,
+                                           unsigned &l)
+{
+    const unsigned b0 = __float_as_uint(x0), b1 = __float_as_uint(x1);
+    const float r0 = x0 - __uint_as_float(b0 & 0xffff0000u);
+    const float r1 = x1 - __uint_as_float(b1 & 0xffff0000u);
+    const unsigned c0 = __float_as_uint(r0), c1 = __float_as_uint(r1);
+    const float q0 = r0 - __uint_as_float(c0 & 0xffff0000u);
+    const float q1 = r1 - __uint_as_float(c1 & 0xffff0000u);
+    h = (b0 >> 16) | (b1 & 0xffff0000u);
+    m = (c0 >> 16) | (c1 & 0xffff0000u);
+    l = (__float_as_uint(q0) >> 16) | (__float_as_uint(q1) & 0xffff0000u);
+}
+
+// Split eight FP32 values into the three BF16 operand vectors.
+__device__ __forceinline__ Split3 split8(const float (&x)[8])
+{
+    u32x4 h, m, l;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        unsigned a, b, c;
+        split_pair(x[2 * q], x[2 * q + 1], a, b, c);
+        h[q] = a;
+        m[q] = b;
+        l[q] = c;
+    }
+    return {__builtin_bit_cast(v8bf, h), __builtin_bit_cast(v8bf, m), __builtin_bit_cast(v8bf, l)};
+}
+
+__device__ __forceinline__ v8bf negx(v8bf v)
+{
+    u32x4 u = __builtin_bit_cast(u32x4, v);
+    u ^= 0x80008000u;
+    return __builtin_bit_cast(v8bf, u);
+}
+
+__device__ __forceinline__ Split3 negx3(const Split3 &a) { return {negx(a.h), negx(a.m), negx(a.l)}; }
+
 __device__ __forceinline__ v8bf neg8(v8bf v)
 {
     v8bf r;

@@ -50,6 +50,7 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     L.buf_bytes[1] = per[1];
     L.buf[0] = take(per[0]);
     L.buf[1] = take(per[1]);
+    L.ttab = take(p.tt.total * 8);
     L.psum = take(p.n * p.n * 16);
     L.pm = take(p.n * p.n * 16);
     L.phi_bytes = p.npad * p.npad * 16 * 4;
@@ -83,7 +84,7 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
     if (!std::isfinite(q.delta)) return fail(NPF_E_INVALID, "delta must be finite");
     if (q.hbm_budget_bytes < 0 || q.block_modes < 0)
         return fail(NPF_E_INVALID, "negative budget or block size");
-    if (q.n > 4096) return fail(NPF_E_UNSUPPORTED, "n > 4096 is not supported");
+    if (q.n > 256) return fail(NPF_E_UNSUPPORTED, "n > 256 is not supported by the MFMA kernels");
 
     npf_plan_s *p = new (std::nothrow) npf_plan_s();
     if (!p) return fail(NPF_E_INVALID, "out of host memory");
@@ -93,13 +94,18 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
     p->prec = q.precision;
     p->esz = (q.precision == NPF_FP64) ? 16 : 8;
     p->npad = round_up(q.n, 32);
-    p->n_parts = 0;
     for (int m = 0; m <= p->N; ++m) {
         p->U[m] = binom(q.n + m - 1, m);
         if (p->U[m] <= 0 || p->U[m] > (int64_t(1) << 40)) {
             delete p;
             return fail(NPF_E_UNSUPPORTED, "tuple count overflows the supported range");
         }
+    }
+    p->tt.maxlen = p->N - 1;
+    for (int m = 1; m <= p->N - 1; ++m) {
+        p->tt.count[m] = p->U[m];
+        p->tt.off[m] = p->tt.total;
+        p->tt.total += p->U[m];
     }
     // Block size over output modes: shrink the outermost (mode) dimension until the
     // working set fits the limit, then balance the blocks -- Alg. 1 steps 6-15 applied to

@@ -3,8 +3,9 @@
 // for every sorted mode prefix p (length i-1, rank rp) and sorted state suffix s (length
 // M-i, rank rs).  Per (p, s) item this is a [t x a] x [a x j] complex product whose right
 // operand rows are gathered from the symmetric storage of T_{i-1}; the gather table
-// rank(sort(a U s)) is built once per item in LDS.  Wave w of a workgroup owns 16 modes;
-// every wave sweeps all t tiles of the item so each gathered row is read once.
+// rank(sort(a U s)) is built once per item in LDS (double-buffered, one barrier per item).
+// Wave w of a workgroup owns 16 modes; every wave sweeps all t tiles of the item so each
+// gathered row is read once.  Phi stays in LDS when it fits.
 #include "npf_device.h"
 #include "npf_internal.h"
 #include "npf_mfma.h"
@@ -15,17 +16,25 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kMaxN = 256;          // states supported by the MFMA chain kernels
+constexpr int kMaxN = 256;          // states supported by the MFMA kernels
+constexpr int64_t kResidentBytes = 128 * 1024;
 
 struct StageArgs {
     const void *in;        // T_{i-1}: [U_{i-1}][U_in][Jpad]
     void *out;             // T_i:     [U_i][U_suf][Jpad]
     const void *phiE;      // staged Phi (engine layout)
+    const uint64_t *ptab;  // sorted (i-1)-tuples (unused when i == 1)
+    const uint64_t *stab;  // sorted (M-i)-tuples (unused when i == M)
     int64_t n, npad, Jpad, U_suf, U_in, items;
     int M, i;
 };
 
-template <Eng E, int NTT>
+template <Eng E> constexpr int64_t phi_bytes(int64_t npad)
+{
+    return (E == Eng::F64 ? 16 : (E == Eng::F32 ? 8 : 12)) * npad * npad;
+}
+
+template <Eng E, int NTT, bool RES>
 __global__ void __launch_bounds__(kThreads)
 stage_mfma(StageArgs a)
 {
@@ -33,33 +42,40 @@ stage_mfma(StageArgs a)
     using acc_t = typename T::acc;
     using real = typename T::real;
     using cplx = typename T::cplx;
+    extern __shared__ __align__(16) char lds[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
     const bool wave_on = jw < a.Jpad;
     const int ntt = int(a.npad / 16);
+    const int64_t N2 = a.npad * a.npad;
 
-    __shared__ int32_t sidx[kMaxN];
-    __shared__ int32_t sp[kMaxOrder], ss[kMaxOrder];
-    __shared__ int64_t sbase;
-    __shared__ int32_t sm;
+    __shared__ int32_t sidx[2][kMaxN];
+
+    const char *phiB = static_cast<const char *>(a.phiE);
+    if constexpr (RES) {
+        const int4 *gp = reinterpret_cast<const int4 *>(a.phiE);
+        int4 *lp = reinterpret_cast<int4 *>(lds);
+        for (int64_t x = threadIdx.x; x < phi_bytes<E>(a.npad) / 16; x += blockDim.x) lp[x] = gp[x];
+        phiB = lds;      // the barrier of the first item orders these writes
+    }
 
     const int sufl = a.M - a.i;       // suffix length
-    for (int64_t it = blockIdx.x; it < a.items; it += gridDim.x) {
+    int parity = 0;
+    for (int64_t it = blockIdx.x; it < a.items; it += gridDim.x, parity ^= 1) {
         const int64_t rp = it / a.U_suf, rs = it % a.U_suf;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            colex_unrank(rp, a.i - 1, a.n, sp);
-            colex_unrank(rs, sufl, a.n, ss);
-            sm = (a.i > 1) ? sp[a.i - 2] : 0;
-            sbase = (a.i > 1) ? colex_rank(sp, a.i - 1) : 0;
+        int32_t p[NPF_MAX_ORDER], s[NPF_MAX_ORDER];
+        if (a.i > 1) unpack_tuple(a.ptab[rp], a.i - 1, p);
+        if (sufl > 0) unpack_tuple(a.stab[rs], sufl, s);
+        const int m = (a.i > 1) ? p[a.i - 2] : 0;
+        if (threadIdx.x < a.n) {
+            InsertRank ir;
+            ir.init(s, sufl);
+            sidx[parity][threadIdx.x] = int32_t(ir.rank(int32_t(threadIdx.x)));
         }
         __syncthreads();
-        for (int x = threadIdx.x; x < a.n; x += blockDim.x)
-            sidx[x] = int32_t(colex_rank_insert(int32_t(x), ss, sufl));
-        __syncthreads();
         if (!wave_on) continue;
-        const int m = sm;
+        const int32_t *idx = sidx[parity];
         const int tt0 = m / 16;
         const cplx *src = static_cast<const cplx *>(a.in) + rp * a.U_in * a.Jpad + jw + c;
 
@@ -68,11 +84,11 @@ stage_mfma(StageArgs a)
         for (int tt = 0; tt < NTT; ++tt) sr[tt] = si[tt] = acc_t{0, 0, 0, 0};
 
         if constexpr (E != Eng::BF3) {
-            const cplx *Ph = static_cast<const cplx *>(a.phiE);
+            const cplx *Ph = reinterpret_cast<const cplx *>(phiB);
             for (int64_t a0 = 0; a0 < a.npad; a0 += 4) {
                 const int64_t ar = a0 + g;
                 cplx x;
-                if (ar < a.n) x = src[int64_t(sidx[ar]) * a.Jpad];
+                if (ar < a.n) x = src[int64_t(idx[ar]) * a.Jpad];
                 else x = cplx{0, 0};
 #pragma unroll
                 for (int tt = 0; tt < NTT; ++tt) {
@@ -85,32 +101,31 @@ stage_mfma(StageArgs a)
                 }
             }
         } else {
-            const __bf16 *Ph = static_cast<const __bf16 *>(a.phiE);
-            const int64_t plane = a.npad * a.npad;
+            const __bf16 *Ph = reinterpret_cast<const __bf16 *>(phiB);
             for (int64_t a0 = 0; a0 < a.npad; a0 += 32) {
                 Split3 xr, xi;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int64_t ar = a0 + 8 * g + s;
+                for (int q = 0; q < 8; ++q) {
+                    const int64_t ar = a0 + 8 * g + q;
                     float2 x = make_float2(0.f, 0.f);
-                    if (ar < a.n) x = src[int64_t(sidx[ar]) * a.Jpad];
+                    if (ar < a.n) x = src[int64_t(idx[ar]) * a.Jpad];
                     __bf16 h, mm, l;
                     split3(x.x, h, mm, l);
-                    xr.h[s] = h; xr.m[s] = mm; xr.l[s] = l;
+                    xr.h[q] = h; xr.m[q] = mm; xr.l[q] = l;
                     split3(x.y, h, mm, l);
-                    xi.h[s] = h; xi.m[s] = mm; xi.l[s] = l;
+                    xi.h[q] = h; xi.m[q] = mm; xi.l[q] = l;
                 }
 #pragma unroll
                 for (int tt = 0; tt < NTT; ++tt) {
                     if (tt < tt0 || tt >= ntt) continue;
                     const int64_t pidx = ((a0 / 8 + g) * a.npad + tt * 16 + c) * 8;
                     Split3 pr, pi;
-                    pr.h = *reinterpret_cast<const v8bf *>(Ph + 0 * plane + pidx);
-                    pr.m = *reinterpret_cast<const v8bf *>(Ph + 1 * plane + pidx);
-                    pr.l = *reinterpret_cast<const v8bf *>(Ph + 2 * plane + pidx);
-                    pi.h = *reinterpret_cast<const v8bf *>(Ph + 3 * plane + pidx);
-                    pi.m = *reinterpret_cast<const v8bf *>(Ph + 4 * plane + pidx);
-                    pi.l = *reinterpret_cast<const v8bf *>(Ph + 5 * plane + pidx);
+                    pr.h = *reinterpret_cast<const v8bf *>(Ph + 0 * N2 + pidx);
+                    pr.m = *reinterpret_cast<const v8bf *>(Ph + 1 * N2 + pidx);
+                    pr.l = *reinterpret_cast<const v8bf *>(Ph + 2 * N2 + pidx);
+                    pi.h = *reinterpret_cast<const v8bf *>(Ph + 3 * N2 + pidx);
+                    pi.m = *reinterpret_cast<const v8bf *>(Ph + 4 * N2 + pidx);
+                    pi.l = *reinterpret_cast<const v8bf *>(Ph + 5 * N2 + pidx);
                     const Split3 pn = neg3(pi);
                     sr[tt] = mm6(pr, xr, sr[tt]);
                     sr[tt] = mm6(pn, xi, sr[tt]);
@@ -119,8 +134,7 @@ stage_mfma(StageArgs a)
                 }
             }
         }
-        // Store T_i rows (p U t, s) for t >= m.
-        const int64_t base = sbase;
+        // Store T_i rows (p U t, s) for t >= m; rank(p U t) = rp + binom(t + i - 1, i).
         cplx *dst = static_cast<cplx *>(a.out) + rs * a.Jpad + jw + c;
 #pragma unroll
         for (int tt = 0; tt < NTT; ++tt) {
@@ -129,11 +143,26 @@ stage_mfma(StageArgs a)
             for (int r = 0; r < 4; ++r) {
                 const int64_t t = int64_t(tt) * 16 + out_row<E>(r, g);
                 if (t < m || t >= a.n) continue;
-                const int64_t row = base + colex_term(t, a.i);
+                const int64_t row = rp + colex_term_c(t, a.i);
                 dst[row * a.U_suf * a.Jpad] = cplx{sr[tt][r], si[tt][r]};
             }
         }
     }
+}
+
+template <Eng E, int NTT, bool RES>
+void launch_one(const dim3 &grid, const StageArgs &sa, hipStream_t s)
+{
+    const size_t shm = RES ? size_t(phi_bytes<E>(sa.npad)) : 0;
+    if (RES) {
+        static bool attr = false;
+        if (!attr) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&stage_mfma<E, NTT, RES>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(kResidentBytes));
+            attr = true;
+        }
+    }
+    hipLaunchKernelGGL((stage_mfma<E, NTT, RES>), grid, dim3(kThreads), shm, s, sa);
 }
 
 template <Eng E>
@@ -141,17 +170,24 @@ hipError_t launch_stage_eng(const StageArgs &sa, int ntt, int64_t groups, int64_
                             hipStream_t s)
 {
     const dim3 grid{unsigned(groups), unsigned(jgroups), 1u};
+    const bool res = phi_bytes<E>(sa.npad) <= kResidentBytes;
+#define NPF_STAGE_CASE(K)                                                   \
+    case K:                                                                 \
+        if (res) launch_one<E, K, true>(grid, sa, s);                       \
+        else launch_one<E, K, false>(grid, sa, s);                          \
+        break;
     switch (ntt) {
-    case 2: hipLaunchKernelGGL((stage_mfma<E, 2>), grid, dim3(kThreads), 0, s, sa); break;
-    case 4: hipLaunchKernelGGL((stage_mfma<E, 4>), grid, dim3(kThreads), 0, s, sa); break;
-    case 6: hipLaunchKernelGGL((stage_mfma<E, 6>), grid, dim3(kThreads), 0, s, sa); break;
-    case 8: hipLaunchKernelGGL((stage_mfma<E, 8>), grid, dim3(kThreads), 0, s, sa); break;
-    case 10: hipLaunchKernelGGL((stage_mfma<E, 10>), grid, dim3(kThreads), 0, s, sa); break;
-    case 12: hipLaunchKernelGGL((stage_mfma<E, 12>), grid, dim3(kThreads), 0, s, sa); break;
-    case 14: hipLaunchKernelGGL((stage_mfma<E, 14>), grid, dim3(kThreads), 0, s, sa); break;
-    case 16: hipLaunchKernelGGL((stage_mfma<E, 16>), grid, dim3(kThreads), 0, s, sa); break;
+        NPF_STAGE_CASE(2)
+        NPF_STAGE_CASE(4)
+        NPF_STAGE_CASE(6)
+        NPF_STAGE_CASE(8)
+        NPF_STAGE_CASE(10)
+        NPF_STAGE_CASE(12)
+        NPF_STAGE_CASE(14)
+        NPF_STAGE_CASE(16)
     default: return hipErrorInvalidValue;
     }
+#undef NPF_STAGE_CASE
     return hipGetLastError();
 }
 
@@ -162,11 +198,15 @@ bool stage_mfma_supported(const npf_plan_s *p) { return p->n <= kMaxN; }
 hipError_t launch_stage_mfma(const ChainArgs &ca, int i)
 {
     const npf_plan_s &p = *ca.plan;
+    if (bf3_small_supported(&p)) return launch_stage_bf3(ca, i);
     const int M = ca.M;
+    const uint64_t *tt = reinterpret_cast<const uint64_t *>(ca.ws + p.lay.ttab);
     StageArgs sa;
     sa.in = ca.ws + p.lay.buf[(i - 1) % 2];
     sa.out = ca.ws + p.lay.buf[i % 2];
     sa.phiE = ca.ws + p.lay.phi + 16 * p.npad * p.npad;
+    sa.ptab = tt + p.tt.off[i - 1 > 0 ? i - 1 : 1];
+    sa.stab = tt + p.tt.off[M - i > 0 ? M - i : 1];
     sa.n = p.n;
     sa.npad = p.npad;
     sa.Jpad = p.Jpad;
@@ -177,7 +217,7 @@ hipError_t launch_stage_mfma(const ChainArgs &ca, int i)
     sa.i = i;
     const int ntt = int(p.npad / 16);
     const int64_t jgroups = (p.Jpad + 63) / 64;
-    int64_t groups = 8192 / jgroups;
+    int64_t groups = 1024 / jgroups;
     if (groups > sa.items) groups = sa.items;
     if (groups < 1) groups = 1;
     switch (p.prec) {
