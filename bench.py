@@ -51,7 +51,7 @@ def kernel_work(name, sysm, plan):
     if what.startswith("stage"):
         i = int(what[5:])
         return (8.0 * J * n * U[i] * U[M - i], 8.0 * J * (U[i - 1] * U[M - i + 1] + U[i] * U[M - i]),
-                "alu", False)
+                "mfma", True)
     if what == "last_to_c":
         return 8.0 * J * n * U[M], 8.0 * J * (U[M - 1] * n) + 16.0 * J * U[M], "alu", False
     if what == "normal_form":
@@ -64,6 +64,8 @@ def kernel_work(name, sysm, plan):
 
 
 def time_path(sysm, s, precision, steps, warmup, device, profile):
+    """Time `steps` steps on a dedicated stream (graph replay after the first call), then,
+    if `profile`, run the same steps eagerly with HIP events around every kernel launch."""
     import torch
     from paper_2509_08968_amd import binding as B
 
@@ -73,42 +75,48 @@ def time_path(sysm, s, precision, steps, warmup, device, profile):
     mk = lambda: B.Plan(n, N, precision, s.eps, s.tau, s.delta)
     plan0 = mk()
     ws = plan0.workspace(device)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream(device=device)       # default priority
 
     def step(plan):
         plan.run(sysm.tensors, sysm.U, sysm.V, sysm.lam, ws, P, npf, stream)
 
+    torch.cuda.synchronize()
     for _ in range(warmup):
         p = mk()
         step(p)
         p.close()
     torch.cuda.synchronize()
-    plans = []
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(steps):
         p = mk()                       # Alg. 1 block sizing is part of every step
-        if profile:
-            p.profile(True)
         step(p)
-        plans.append(p)
+        p.close()
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / steps
-    ktimes = {}
-    for p in plans:
-        if profile:
-            for k, (cnt, tot) in p.kernel_times().items():
-                c0, t_ = ktimes.get(k, (0, 0.0))
-                ktimes[k] = (c0 + cnt, t_ + tot)
-    for p in plans:
-        p.close()
-    out = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "kernels": ktimes,
+    out = {"ms_per_step": ms, "wall_ms_per_step": 1e3 * wall / steps, "kernels": {},
            "P": {M: P[M - 2].cpu().numpy() for M in range(2, N + 1)}, "npf": npf.cpu().numpy(),
            "plan": plan0}
+    if profile:
+        plans = []
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        for _ in range(steps):
+            p = mk()
+            p.profile(True)            # eager launches, an event pair around each kernel
+            step(p)
+            plans.append(p)
+        e3.record(stream)
+        torch.cuda.synchronize()
+        out["eager_ms_per_step"] = e2.elapsed_time(e3) / steps
+        for p in plans:
+            for k, (cnt, tot) in p.kernel_times().items():
+                c0, t_ = out["kernels"].get(k, (0, 0.0))
+                out["kernels"][k] = (c0 + cnt, t_ + tot)
+            p.close()
     return out
 
 
@@ -147,7 +155,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n64-o3-blocksparse")
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -213,7 +221,8 @@ def main():
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak, "traffic": None, "kernel": name,
                 "avg_launch_ms": tot / cnt, "launches_per_step": cnt / args.steps,
-                "share_of_step": tot / args.steps / res["ms_per_step"]}
+                "share_of_step": tot / args.steps / res["ms_per_step"],
+                "timing": "HIP events around every launch, eager pass of the same steps"}
         if mfma:
             roof["executed_mfma_frac"] = achieved * SPLIT_PRODUCTS[args.precision] / peak
         log(f"[bench] kernels: " + ", ".join(f"{k}={v[1] / args.steps:.3f}ms"
@@ -229,6 +238,7 @@ def main():
         "config": {"workload": args.workload, "n": s.n, "orders": s.orders,
                    "precision": args.precision, "modal_entries_per_step": entries,
                    "block_modes": plan.block_modes, "blocks": plan.n_blocks},
+        "eager_ms_per_step": res.get("eager_ms_per_step"),
         "rel_err_vs_oracle": err,
         "fp64_gpu": fp64,
         "roofline": roof,

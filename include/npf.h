@@ -85,7 +85,15 @@ typedef struct npf_problem {
     double delta;              /* excitation magnitude of eq. (7)                     */
     int64_t hbm_budget_bytes;  /* workspace cap, the M_limit of Alg. 1; 0 = none      */
     int64_t block_modes;       /* output modes per block; 0 = chosen by the planner   */
+    int32_t flags;             /* NPF_FLAG_* bits                                      */
+    int32_t reserved;
 } npf_problem;
+
+/* npf_run replays a HIP graph of its launch sequence when called again with the same
+ * problem, pointers, descriptors and stream (the graph is captured on the first call).
+ * This flag disables that and always launches eagerly.  Graphs are never used on the
+ * NULL stream, on a stream that is already capturing, or while profiling. */
+#define NPF_FLAG_NO_GRAPH 1
 
 typedef struct npf_plan_s *npf_plan_t;
 
@@ -134,7 +142,9 @@ int npf_finalize(npf_plan_t plan, const void *U, const void *V, const void *P_su
 /* The whole hot path, all orders 2..N and all blocks, with the last contraction, the
  * divisor, the division and the reduction fused: A[M-2] describes A_M.  Writes
  * P_out[(M-2)*n*n + j*n + k] (nullable) and NPF (nullable).  Deterministic: two calls on
- * the same inputs give bitwise equal results. */
+ * the same inputs give bitwise equal results.  See NPF_FLAG_NO_GRAPH for graph replay;
+ * a replayed graph reads the device buffers afresh, so new input values are honoured as
+ * long as the pointers and descriptors are unchanged. */
 int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
             const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
             void *stream);

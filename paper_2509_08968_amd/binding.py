@@ -54,7 +54,11 @@ class NpfProblem(ctypes.Structure):
         ("n", ctypes.c_int64), ("order_max", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("eps", ctypes.c_double), ("tau", ctypes.c_double), ("delta", ctypes.c_double),
         ("hbm_budget_bytes", ctypes.c_int64), ("block_modes", ctypes.c_int64),
+        ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
+
+
+NPF_FLAG_NO_GRAPH = 1
 
 
 class NpfPlanReport(ctypes.Structure):
@@ -141,9 +145,9 @@ class Plan:
 
     def __init__(self, n: int, order_max: int, precision: str = "fp64", eps: float = 1e-9,
                  tau: float = 1e-2, delta: float = 1.0, budget_bytes: int = 0,
-                 block_modes: int = 0):
+                 block_modes: int = 0, graph: bool = True):
         prob = NpfProblem(n, order_max, PRECISIONS[precision], eps, tau, delta, budget_bytes,
-                          block_modes)
+                          block_modes, 0 if graph else NPF_FLAG_NO_GRAPH, 0)
         h = ctypes.c_void_p()
         _check(lib().npf_plan_create(ctypes.byref(prob), ctypes.byref(h)), "npf_plan_create")
         self._h = h
@@ -288,12 +292,12 @@ def upload_system(sys, device, sparse: Optional[bool] = None) -> DeviceSystem:
 
 
 def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0,
-            block_modes: int = 0, sparse: Optional[bool] = None):
+            block_modes: int = 0, sparse: Optional[bool] = None, graph: bool = True):
     """Run the fused hot path on one system; returns (NPF, {M: P_M}) as numpy arrays."""
     import torch
     dev = upload_system(sys, device, sparse)
     plan = Plan(sys.n, sys.order_max, precision, sys.eps, sys.tau, sys.delta, budget_bytes,
-                block_modes)
+                block_modes, graph)
     ws = plan.workspace(device)
     n, N = sys.n, sys.order_max
     P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)

@@ -1,6 +1,8 @@
 // C ABI entry points: argument checks, block loops and kernel sequencing.
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "npf_internal.h"
 
@@ -171,6 +173,36 @@ extern "C" int npf_finalize(npf_plan_t plan, const void *U, const void *V, const
                      "finalize");
 }
 
+namespace {
+
+// The launch sequence of npf_run (eager).
+int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
+              const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s);
+
+// Graph cache: one instantiated graph per distinct argument set (problem, descriptors,
+// pointers, stream), least recently used evicted.
+struct GraphKey {
+    npf_problem prob;
+    npf_tensor A[NPF_MAX_ORDER];
+    const void *ptr[7];
+    hipStream_t stream;
+};
+
+bool same_key(const GraphKey &a, const GraphKey &b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    uint64_t used;
+};
+
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+constexpr size_t kMaxGraphs = 8;
+
+}  // namespace
+
 extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
                        const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
                        void *stream)
@@ -182,6 +214,58 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
     for (int M = 2; M <= plan->N; ++M)
         if ((rc = check_tensor(plan, &A[M - 2], M))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    bool graph = !(plan->prob.flags & NPF_FLAG_NO_GRAPH) && !plan->prof.on && s != nullptr;
+    if (graph) {
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone)
+            graph = false;
+    }
+    if (!graph) return run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
+
+    GraphKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.prob = plan->prob;
+    for (int M = 2; M <= plan->N; ++M) key.A[M - 2] = A[M - 2];
+    const void *ptrs[7] = {U, V, lambda, ws, P_out, npf_out, reinterpret_cast<const void *>(ws_bytes)};
+    std::memcpy(key.ptr, ptrs, sizeof(ptrs));
+    key.stream = s;
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (auto &e : g_graphs)
+        if (same_key(e.key, key)) {
+            e.used = ++g_graph_clock;
+            return check_hip(hipGraphLaunch(e.exec, s), "graph launch");
+        }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
+    rc = run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (rc != NPF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ec != hipSuccess || !g) return check_hip(ec != hipSuccess ? ec : hipErrorUnknown, "graph capture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return check_hip(ei, "graph instantiate");
+    if (g_graphs.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < g_graphs.size(); ++i)
+            if (g_graphs[i].used < g_graphs[lru].used) lru = i;
+        (void)hipGraphExecDestroy(g_graphs[lru].exec);
+        g_graphs.erase(g_graphs.begin() + lru);
+    }
+    g_graphs.push_back({key, exec, ++g_graph_clock});
+    return check_hip(hipGraphLaunch(exec, s), "graph launch");
+}
+
+namespace {
+
+int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
+              const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s)
+{
+    int rc = NPF_OK;
     char *w = static_cast<char *>(ws);
     const int64_t nn = plan->n * plan->n;
     double *psum = reinterpret_cast<double *>(w + plan->lay.psum);
@@ -216,3 +300,5 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
     }
     return rc;
 }
+
+}  // namespace

@@ -65,7 +65,7 @@ __device__ __forceinline__ void split_x(const float2 (&x)[8], Split3 &xr, Split3
 }
 
 // ------------------------------------------------------------------ fused last stage
-template <int NP>
+template <int NP, int M>
 __global__ void __launch_bounds__(kThreads)
 fused_bf3(Bf3Args a)
 {
@@ -120,24 +120,28 @@ fused_bf3(Bf3Args a)
     }
     if (wave_on)
     for (; it < a.items; it += gridDim.x) {
-        float2 xc[KC][8];
+        // Split this item's rows, then start loading the next item's into the same registers.
+        Split3 xr[KC], xi[KC], xn_[KC];
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-            for (int s = 0; s < 8; ++s) xc[kc][s] = xn[kc][s];
+        for (int kc = 0; kc < KC; ++kc) {
+            split_x(xn[kc], xr[kc], xi[kc]);
+            xn_[kc] = negx3(xi[kc]);
+        }
         const uint64_t pk = pk_next;
         const int64_t itn = it + gridDim.x;
         if (itn < a.items) {
             load_x(itn);
             pk_next = a.ptab[itn];
         }
-        // Item constants.
-        int32_t p[NPF_MAX_ORDER];
-        unpack_tuple_reg(pk, a.M - 1, p);
+        // Item constants (M is a compile-time constant: the tuple lives in registers).
+        int32_t p[M - 1];
+#pragma unroll
+        for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
         double2 lam_p = Llam[p[0]];
         double den = 1.0;
         int run = 1;
-        for (int q = 1; q < a.M - 1; ++q) {
+#pragma unroll
+        for (int q = 1; q < M - 1; ++q) {
             lam_p = add_fp64(lam_p, Llam[p[q]]);
             if (p[q] == p[q - 1]) {
                 ++run;
@@ -146,16 +150,9 @@ fused_bf3(Bf3Args a)
                 run = 1;
             }
         }
-        const int m = p[a.M - 2];
+        const int m = p[M - 2];
         const double w_gt = -1.0 / den, w_eq = -1.0 / (den * double(run + 1));
         const float w_gt_f = float(w_gt), w_eq_f = float(w_eq);
-
-        Split3 xr[KC], xi[KC], xn_[KC];
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            split_x(xc[kc], xr[kc], xi[kc]);
-            xn_[kc] = negx3(xi[kc]);
-        }
 
         v4f rr[NKT], ri[NKT];
 #pragma unroll
@@ -230,16 +227,18 @@ fused_bf3(Bf3Args a)
         for (int kt = 0; kt < NKT; ++kt) {
             const int k = kt * 16 + c;
             float2 z = Lz32[p[0] * NP + k];
-            for (int q = 1; q < a.M - 1; ++q) {
+#pragma unroll
+            for (int q = 1; q < M - 1; ++q) {
                 const float2 w = Lz32[p[q] * NP + k];
                 z = make_float2(z.x * w.x - z.y * w.y, z.x * w.y + z.y * w.x);
             }
-            const double zr = z.x, zi = z.y;
+            // The item's product zp * R is formed in FP32 (one rounding); the sum over
+            // items is kept in FP64.
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double vr = rr[kt][r], vi = ri[kt][r];
-                pacc_r[kt][r] += vr * zr - vi * zi;
-                pacc_i[kt][r] += vr * zi + vi * zr;
+                const float vr = rr[kt][r], vi = ri[kt][r];
+                pacc_r[kt][r] += double(vr * z.x - vi * z.y);
+                pacc_i[kt][r] += double(vr * z.y + vi * z.x);
             }
         }
     }
@@ -258,7 +257,7 @@ fused_bf3(Bf3Args a)
 }
 
 // ------------------------------------------------------------------ one chain stage
-template <int NP>
+template <int NP, int SUF>
 __global__ void __launch_bounds__(kThreads)
 stage_bf3(Bf3Args a)
 {
@@ -275,15 +274,28 @@ stage_bf3(Bf3Args a)
     const int g = lane >> 4, c = lane & 15;
     const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
     const bool wave_on = jw < a.Jpad;
-    const int sufl = a.M - a.i;
     const float2 *X = static_cast<const float2 *>(a.X);
 
     auto build_idx = [&](int64_t it, int buf) {
         const int64_t rs = it % a.U_suf;
-        int32_t s[NPF_MAX_ORDER];
-        unpack_tuple_reg(sufl > 0 ? a.stab[rs] : 0, sufl, s);
-        if (threadIdx.x < a.n)
-            sidx[buf][threadIdx.x] = int32_t(rank_insert_reg(int32_t(threadIdx.x), s, sufl));
+        const uint64_t pk = a.stab[rs];
+        if (threadIdx.x < a.n) {
+            // rank(sort({x} U s)) for the sorted suffix s (SUF entries, in registers).
+            const int32_t x = int32_t(threadIdx.x);
+            int64_t r = 0;
+            int q = 0;
+#pragma unroll
+            for (int l = 0; l < SUF; ++l) {
+                const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
+                if (sl <= x) {
+                    r += colex_term_c(sl, l + 1);
+                    ++q;
+                } else {
+                    r += colex_term_c(sl, l + 2);
+                }
+            }
+            sidx[buf][threadIdx.x] = int32_t(r + colex_term_c(x, q + 1));
+        }
     };
     float2 xn[KC][8];
     auto gather_x = [&](int64_t it, int buf) {
@@ -307,11 +319,12 @@ stage_bf3(Bf3Args a)
     __syncthreads();          // also orders the LDS copy of Phi
     if (it < a.items && wave_on) gather_x(it, 0);
     for (; it < a.items; it += gridDim.x, buf ^= 1) {
-        float2 xc[KC][8];
+        Split3 xr[KC], xi[KC], xn_[KC];
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-            for (int s = 0; s < 8; ++s) xc[kc][s] = xn[kc][s];
+        for (int kc = 0; kc < KC; ++kc) {
+            split_x(xn[kc], xr[kc], xi[kc]);
+            xn_[kc] = negx3(xi[kc]);
+        }
         const int64_t itn = it + gridDim.x;
         if (itn < a.items) build_idx(itn, buf ^ 1);
         __syncthreads();
@@ -322,12 +335,6 @@ stage_bf3(Bf3Args a)
         int m = 0;
         if (a.i > 1) m = int((a.ptab[rp] >> (8 * (a.i - 2))) & 0xff);
         const int tt0 = m / 16;
-        Split3 xr[KC], xi[KC], xn_[KC];
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            split_x(xc[kc], xr[kc], xi[kc]);
-            xn_[kc] = negx3(xi[kc]);
-        }
 
         v4f sr[NTT], si[NTT];
 #pragma unroll
@@ -388,7 +395,7 @@ Bf3Args base_args(const npf_plan_s *p, char *ws, const double *lam)
 
 bool bf3_small_supported(const npf_plan_s *p)
 {
-    return p->prec == NPF_BF16X3 && (p->npad == 32 || p->npad == 64);
+    return p->prec == NPF_BF16X3 && (p->npad == 32 || p->npad == 64) && p->N <= 4;
 }
 
 hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
@@ -404,14 +411,16 @@ hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, c
     a.M = M;
     const dim3 grid{unsigned(groups), unsigned((p->Jpad + 63) / 64), 1u};
     const size_t shm = size_t(32 * p->npad * p->npad + 16 * p->npad);
-    if (p->npad == 32) {
-        set_lds_limit(fused_bf3<32>, int(shm));
-        hipLaunchKernelGGL(fused_bf3<32>, grid, dim3(kThreads), shm, s, a);
-    } else {
-        set_lds_limit(fused_bf3<64>, int(shm));
-        hipLaunchKernelGGL(fused_bf3<64>, grid, dim3(kThreads), shm, s, a);
+#define NPF_FUSED_CASE(NP_, M_)                                                   \
+    if (p->npad == NP_ && M == M_) {                                             \
+        set_lds_limit(fused_bf3<NP_, M_>, int(shm));                              \
+        hipLaunchKernelGGL((fused_bf3<NP_, M_>), grid, dim3(kThreads), shm, s, a); \
+        return hipGetLastError();                                                 \
     }
-    return hipGetLastError();
+    NPF_FUSED_CASE(32, 2) NPF_FUSED_CASE(32, 3) NPF_FUSED_CASE(32, 4)
+    NPF_FUSED_CASE(64, 2) NPF_FUSED_CASE(64, 3) NPF_FUSED_CASE(64, 4)
+#undef NPF_FUSED_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
@@ -435,14 +444,17 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     if (groups < 1) groups = 1;
     const dim3 grid{unsigned(groups), unsigned(jgroups), 1u};
     const size_t shm = size_t(12 * p.npad * p.npad);
-    if (p.npad == 32) {
-        set_lds_limit(stage_bf3<32>, int(shm));
-        hipLaunchKernelGGL(stage_bf3<32>, grid, dim3(kThreads), shm, ca.stream, a);
-    } else {
-        set_lds_limit(stage_bf3<64>, int(shm));
-        hipLaunchKernelGGL(stage_bf3<64>, grid, dim3(kThreads), shm, ca.stream, a);
+    const int suf = M - i;
+#define NPF_STAGE_CASE(NP_, S_)                                                           \
+    if (p.npad == NP_ && suf == S_) {                                                    \
+        set_lds_limit(stage_bf3<NP_, S_>, int(shm));                                      \
+        hipLaunchKernelGGL((stage_bf3<NP_, S_>), grid, dim3(kThreads), shm, ca.stream, a); \
+        return hipGetLastError();                                                         \
     }
-    return hipGetLastError();
+    NPF_STAGE_CASE(32, 1) NPF_STAGE_CASE(32, 2) NPF_STAGE_CASE(32, 3)
+    NPF_STAGE_CASE(64, 1) NPF_STAGE_CASE(64, 2) NPF_STAGE_CASE(64, 3)
+#undef NPF_STAGE_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace npf

@@ -481,7 +481,7 @@ int64_t fused_groups(const npf_plan_s *p, int M)
 {
     const int64_t items = p->U[M - 1];
     const int64_t jgroups = (p->Jpad + 63) / 64;
-    int64_t g = 512 / jgroups;
+    int64_t g = (bf3_small_supported(p) ? 256 : 512) / jgroups;
     if (g < 1) g = 1;
     return items < g ? items : g;
 }

@@ -109,3 +109,44 @@ def test_linear_limit_on_gpu(torch_dev):
     npf, Ps = B.compute(s, "fp64")
     assert all(np.abs(P).max() == 0 for P in Ps.values())
     assert rel(npf, 0.5 * s.V * s.U.T) < 1e-15
+
+
+def test_graph_replay_matches_eager(torch_dev):
+    """npf_run replays a captured graph: every replay, with unrelated eager work and
+    synchronisations in between, equals the eager result bitwise; new input values behind
+    the same pointers are honoured."""
+    torch, dev = torch_dev
+    s = I.block_sparse_system(48, [2, 3], 3501)
+    print("[graph replay] n=48", flush=True)
+    d = B.upload_system(s, dev)
+    n, N = s.n, s.order_max
+    pe = B.Plan(n, N, "bf16x3", s.eps, s.tau, s.delta, graph=False)
+    pg = B.Plan(n, N, "bf16x3", s.eps, s.tau, s.delta, graph=True)
+    ws_e, ws_g = pe.workspace(dev), pg.workspace(dev)
+    st = torch.cuda.Stream()
+
+    def outs():
+        return (torch.empty((N - 1, n, n), dtype=torch.complex128, device=dev),
+                torch.empty((n, n), dtype=torch.complex128, device=dev))
+
+    Pe, Ne = outs()
+    Pg, Ng = outs()
+    pe.run(d.tensors, d.U, d.V, d.lam, ws_e, Pe, Ne, st)
+    torch.cuda.synchronize()
+    ref_P, ref_N = Pe.clone(), Ne.clone()
+    for rep in range(4):
+        pg.run(d.tensors, d.U, d.V, d.lam, ws_g, Pg, Ng, st)
+        torch.cuda.synchronize()
+        assert torch.equal(Pg, ref_P) and torch.equal(Ng, ref_N), rep
+        junk = torch.randn(1 << 16, device=dev).sum()      # eager work between replays
+        pe.run(d.tensors, d.U, d.V, d.lam, ws_e, Pe, Ne, st)
+        torch.cuda.synchronize()
+        assert float(junk) == float(junk)
+    for t in d.tensors:                                     # new values, same pointers
+        t.tensors["values"].mul_(2.0)
+    torch.cuda.synchronize()
+    pg.run(d.tensors, d.U, d.V, d.lam, ws_g, Pg, Ng, st)
+    pe.run(d.tensors, d.U, d.V, d.lam, ws_e, Pe, Ne, st)
+    torch.cuda.synchronize()
+    assert torch.equal(Pg, Pe) and torch.equal(Ng, Ne)
+    assert torch.allclose(Pg, 2.0 * ref_P, rtol=1e-5, atol=0)
