@@ -34,6 +34,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# Workspace cap per workload (the memory limit of Alg. 1, applied to HBM); 0 = none.
+WORKLOAD_BUDGET = {"n128-o4-dense-resonant": 64 << 30}
+
+
+def reference_modes(s):
+    """Output modes whose P rows and NPF columns the oracle computes: all of them for small
+    systems, else the mode nearest an order-2 resonance and one fixed mode (each mode's
+    chain is independent, so these rows are exact checks)."""
+    import numpy as np
+    if s.n <= 64:
+        return list(range(s.n))
+    lam = s.lam
+    d2 = np.abs(lam[None, :, None] + lam[None, None, :] - lam[:, None, None]).reshape(s.n, -1)
+    return sorted({int(np.argmin(d2.min(1))), 5})
+
+
 def kernel_work(name, sysm, plan):
     """(algorithmic flops, algorithmic HBM bytes, bound, uses MFMA) of ONE launch of a
     kernel, from the shapes (a complex multiply-add counts 8 flops, real x complex 4)."""
@@ -63,7 +79,7 @@ def kernel_work(name, sysm, plan):
     return 0.0, 0.0, "alu", False
 
 
-def time_path(sysm, s, precision, steps, warmup, device, profile):
+def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0):
     """Time `steps` steps on a dedicated stream (graph replay after the first call), then,
     if `profile`, run the same steps eagerly with HIP events around every kernel launch."""
     import torch
@@ -72,7 +88,7 @@ def time_path(sysm, s, precision, steps, warmup, device, profile):
     n, N = s.n, s.order_max
     P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
     npf = torch.empty((n, n), dtype=torch.complex128, device=device)
-    mk = lambda: B.Plan(n, N, precision, s.eps, s.tau, s.delta)
+    mk = lambda: B.Plan(n, N, precision, s.eps, s.tau, s.delta, budget_bytes=budget)
     plan0 = mk()
     ws = plan0.workspace(device)
     stream = torch.cuda.Stream(device=device)       # default priority
@@ -128,13 +144,23 @@ def rel(a, b):
 
 def cpu_baseline(s, entries, target_s=10.0):
     """The oracle as it stands, timed on this host's cores over a bounded sample: the full
-    workload, repeated until about target_s seconds of CPU time have passed."""
+    workload repeated until about target_s seconds have passed (small systems), or one
+    output mode of every order (large systems), scaled to modal entries per second."""
     import oracle
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
+    if s.n > 64:
+        t0 = time.perf_counter()
+        for M in s.orders:
+            oracle.sym(s, M, modes=[0], nthreads=cores)
+        el = time.perf_counter() - t0
+        done = sum(math.comb(s.n + M - 1, M) for M in s.orders)
+        return {"value": done / el, "unit": "modal entries/s", "cores": cores, "kind": "oracle",
+                "sample": f"one output mode (mode 0) of orders {s.orders}: {done} entries in "
+                          f"{el:.1f} s, packed-symmetric FP64 oracle with {cores} OpenMP threads"}
     reps, t0 = 0, time.perf_counter()
     while True:
         for M in s.orders:
@@ -182,27 +208,33 @@ def main():
     sysm = B.upload_system(s, device)
     log(f"[bench] workload {args.workload}: n={s.n} orders={s.orders}")
 
-    # Oracle reference (outside every timed region).
+    # Oracle reference (outside every timed region): P rows and NPF columns of the modes.
     t0 = time.perf_counter()
-    refP = {M: oracle.sym(s, M)["P"] for M in s.orders}
-    ref_npf = oracle.assemble(s, sum(refP.values()))
-    log(f"[bench] oracle reference in {time.perf_counter() - t0:.1f} s")
+    modes = reference_modes(s)
+    refP = {M: oracle.sym(s, M, modes=modes)["P"] for M in s.orders}
+    zeta = s.delta * s.U[modes, :]
+    ref_npf = s.V[:, modes] * (zeta + sum(refP.values())).T
+    log(f"[bench] oracle reference ({len(modes)} modes) in {time.perf_counter() - t0:.1f} s")
 
+    def errors(r):
+        e = {f"P{M}": rel(r["P"][M][modes], refP[M]) for M in s.orders}
+        e["npf"] = rel(r["npf"][:, modes], ref_npf)
+        return e
+
+    budget = WORKLOAD_BUDGET.get(args.workload, 0)
     res = time_path(sysm, s, args.precision, args.steps, args.warmup, device,
-                    not args.no_profile)
+                    not args.no_profile, budget)
     plan = res["plan"]
     entries = plan.modal_entries
     value = entries / (res["ms_per_step"] * 1e-3)
-    err = {f"P{M}": rel(res["P"][M], refP[M]) for M in s.orders}
-    err["npf"] = rel(res["npf"], ref_npf)
+    err = errors(res)
     log(f"[bench] {args.precision}: {res['ms_per_step']:.3f} ms/step, {value:.3e} entries/s, err {err}")
 
     fp64 = None
     if args.precision != "fp64" and not args.no_fp64:
-        r64 = time_path(sysm, s, "fp64", args.steps, args.warmup, device, False)
+        r64 = time_path(sysm, s, "fp64", args.steps, args.warmup, device, False, budget)
         v64 = entries / (r64["ms_per_step"] * 1e-3)
-        e64 = {f"P{M}": rel(r64["P"][M], refP[M]) for M in s.orders}
-        e64["npf"] = rel(r64["npf"], ref_npf)
+        e64 = errors(r64)
         fp64 = {"value": v64, "ms_per_step": r64["ms_per_step"], "rel_err": e64,
                 "speedup_of_selected": v64 and value / v64}
         log(f"[bench] fp64: {r64['ms_per_step']:.3f} ms/step, {v64:.3e} entries/s, err {e64}")
@@ -237,7 +269,8 @@ def main():
         "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": args.workload, "n": s.n, "orders": s.orders,
                    "precision": args.precision, "modal_entries_per_step": entries,
-                   "block_modes": plan.block_modes, "blocks": plan.n_blocks},
+                   "block_modes": plan.block_modes, "blocks": plan.n_blocks,
+                   "workspace_bytes": plan.workspace_bytes, "oracle_checked_modes": modes},
         "eager_ms_per_step": res.get("eager_ms_per_step"),
         "rel_err_vs_oracle": err,
         "fp64_gpu": fp64,

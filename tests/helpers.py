@@ -20,4 +20,6 @@ PARITY_CASES = {
     "n37-o2-dense-odd": lambda: I.dense_system(37, [2], 3104),
     "n20-o3-resonant": lambda: I.resonant_system(20, [2, 3], 3105, n_res2=1, n_res3=1),
     "n1-o2": lambda: I.dense_system(1, [2], 3106),
+    "n72-o3-dense": lambda: I.dense_system(72, [2, 3], 3107),
+    "n130-o2-dense": lambda: I.dense_system(130, [2], 3108),
 }

@@ -150,3 +150,32 @@ def test_graph_replay_matches_eager(torch_dev):
     torch.cuda.synchronize()
     assert torch.equal(Pg, Pe) and torch.equal(Ng, Ne)
     assert torch.allclose(Pg, 2.0 * ref_P, rtol=1e-5, atol=0)
+
+
+@pytest.fixture(scope="module")
+def dense128():
+    """n=128, orders 2-4 dense with planted resonances and the oracle's P rows for two
+    sampled output modes (one of them the mode closest to an order-2 resonance)."""
+    s = I.workload_dense128()
+    lam = s.lam
+    d2 = np.abs(lam[None, :, None] + lam[None, None, :] - lam[:, None, None]).reshape(s.n, -1).min(1)
+    modes = [int(np.argmin(d2)), 5]
+    ref = {M: oracle.sym(s, M, modes=modes)["P"] for M in s.orders}
+    return s, modes, ref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["bf16x3", "fp64"])
+def test_workload_n128_o4_dense_sampled(torch_dev, dense128, precision):
+    """n=128, orders 2-4, dense, under a 64 GiB workspace budget (two output-mode blocks).
+    P_M rows and NPF columns of the sampled modes are compared with the oracle: each mode's
+    chain is independent, so these are exact checks of the full-size run."""
+    torch, dev = torch_dev
+    s, modes, ref = dense128
+    print(f"[n128-o4 {precision}] modes {modes}", flush=True)
+    npf, Ps = B.compute(s, precision, budget_bytes=64 << 30)
+    for M in s.orders:
+        assert rel(Ps[M][modes], ref[M]) <= TOL[precision], f"P_{M}"
+    z = np.stack([s.delta * s.U[i, :] for i in modes])          # [modes, states]
+    npf_cols = s.V[:, modes] * (z + sum(ref.values())).T
+    assert rel(npf[:, modes], npf_cols) <= TOL[precision]
