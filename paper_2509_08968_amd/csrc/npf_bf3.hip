@@ -368,6 +368,143 @@ stage_bf3(Bf3Args a)
     }
 }
 
+// ------------------------------------------------------------------ one chain stage, n > 64
+// Same arithmetic as stage_bf3; a workgroup owns a range of TT t-tiles (grid.z) and keeps
+// only that slice of the Phi^T planes in LDS.  The gathered rows are loaded one K-chunk
+// ahead (the last chunk of an item prefetches the first chunk of the next item).
+template <int NP, int SUF, int TT>
+__global__ void __launch_bounds__(kThreads)
+stage_bf3_tr(Bf3Args a)
+{
+    constexpr int KC = NP / 32, TW = TT * 16, AG = NP / 8;
+    extern __shared__ __align__(16) char lds[];
+    // Gather tables, three buffers in rotation: item k's table is read in iterations k-1
+    // (its first chunk) and k (the others) and rewritten in iteration k+2 before that
+    // iteration's barrier, i.e. after every wave has passed the barrier of iteration k+1.
+    __shared__ int32_t sidx[3][NP];
+    __shared__ int64_t rowoff[TW];
+    const int t_base = int(blockIdx.z) * TW;
+    {
+        // Slice [t_base, t_base + TW) of the six planes [pl][a/8][t][a%8].
+        const int4 *gsrc = reinterpret_cast<const int4 *>(a.phiE);
+        int4 *ldst = reinterpret_cast<int4 *>(lds);
+        for (int x = threadIdx.x; x < 6 * AG * TW; x += blockDim.x) {
+            const int tl = x % TW, ag = (x / TW) % AG, pl = x / (TW * AG);
+            const int t = t_base + tl;
+            ldst[x] = (t < NP) ? gsrc[(int64_t(pl) * AG + ag) * NP + t] : int4{0, 0, 0, 0};
+        }
+        for (int tl = threadIdx.x; tl < TW; tl += blockDim.x)
+            rowoff[tl] = colex_term_c(t_base + tl, a.i) * a.U_suf * a.Jpad;
+    }
+    const __bf16 *Lphi = reinterpret_cast<const __bf16 *>(lds);
+    constexpr int PL = NP * TW;      // elements per LDS plane
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
+    const bool wave_on = jw < a.Jpad;
+    const float2 *X = static_cast<const float2 *>(a.X);
+    const unsigned jp = unsigned(a.Jpad);
+    const int nn = int(a.n);
+
+    auto build_idx = [&](int64_t it, int buf) {
+        const uint64_t pk = a.stab[it % a.U_suf];
+        if (threadIdx.x < a.n) {
+            const int32_t x = int32_t(threadIdx.x);
+            int64_t r = 0;
+            int q = 0;
+#pragma unroll
+            for (int l = 0; l < SUF; ++l) {
+                const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
+                if (sl <= x) {
+                    r += colex_term_c(sl, l + 1);
+                    ++q;
+                } else {
+                    r += colex_term_c(sl, l + 2);
+                }
+            }
+            sidx[buf][threadIdx.x] = int32_t(r + colex_term_c(x, q + 1));
+        }
+    };
+    // last(p) of an item, and whether this workgroup's t-range has any t >= last(p).
+    auto item_m = [&](int64_t it) {
+        return (a.i > 1) ? int((a.ptab[it / a.U_suf] >> (8 * (a.i - 2))) & 0xff) : 0;
+    };
+    auto active = [&](int m) { return t_base + TW > m; };
+    auto load_chunk = [&](int64_t it, int buf, int kc, float2 (&dst)[8]) {
+        const float2 *src = X + (it / a.U_suf) * a.U_in * a.Jpad + jw + c;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int ar = kc * 32 + 8 * g + q;
+            dst[q] = ar < nn ? src[uint64_t(unsigned(sidx[buf][ar])) * jp] : make_float2(0.f, 0.f);
+        }
+    };
+
+    int64_t it = blockIdx.x;
+    int buf = 0;
+    float2 cur[8];
+    if (it < a.items) build_idx(it, 0);
+    __syncthreads();          // also orders the LDS slice of Phi
+    if (it < a.items && wave_on && active(item_m(it))) load_chunk(it, 0, 0, cur);
+    for (; it < a.items; it += gridDim.x, buf = (buf == 2) ? 0 : buf + 1) {
+        const int64_t itn = it + gridDim.x;
+        const int nbuf = (buf == 2) ? 0 : buf + 1;
+        if (itn < a.items) build_idx(itn, nbuf);
+        __syncthreads();
+        if (!wave_on) continue;
+        const int m = item_m(it);
+        const bool next_on = itn < a.items && active(item_m(itn));
+        if (!active(m)) {
+            if (next_on) load_chunk(itn, nbuf, 0, cur);
+            continue;
+        }
+        const int tt0 = (m > t_base) ? (m - t_base) / 16 : 0;
+        v4f sr[TT], si[TT];
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt) sr[tt] = si[tt] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            float2 nxt[8];
+            if (kc + 1 < KC) load_chunk(it, buf, kc + 1, nxt);
+            else if (next_on) load_chunk(itn, nbuf, 0, nxt);
+            Split3 xr, xi;
+            split_x(cur, xr, xi);
+            const Split3 xng = negx3(xi);
+#pragma unroll
+            for (int tt = 0; tt < TT; ++tt) {
+                if (tt < tt0) continue;
+                const int pidx = ((kc * 4 + g) * TW + tt * 16 + c) * 8;
+                Split3 pr, pi;
+                pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PL + pidx);
+                pr.m = *reinterpret_cast<const v8bf *>(Lphi + 1 * PL + pidx);
+                pr.l = *reinterpret_cast<const v8bf *>(Lphi + 2 * PL + pidx);
+                pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PL + pidx);
+                pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PL + pidx);
+                pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PL + pidx);
+                sr[tt] = mm6(pr, xr, sr[tt]);
+                sr[tt] = mm6(pi, xng, sr[tt]);
+                si[tt] = mm6(pr, xi, si[tt]);
+                si[tt] = mm6(pi, xr, si[tt]);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+        }
+        const int64_t rp = it / a.U_suf, rs = it % a.U_suf;
+        float2 *dst = static_cast<float2 *>(a.out) + (rp * a.U_suf + rs) * a.Jpad + jw + c;
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt) {
+            if (tt < tt0) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int tl = tt * 16 + 4 * g + r;
+                const int t = t_base + tl;
+                if (t < m || t >= nn) continue;
+                dst[rowoff[tl]] = make_float2(sr[tt][r], si[tt][r]);
+            }
+        }
+    }
+}
+
 template <typename K>
 void set_lds_limit(K kernel, int bytes)
 {
@@ -442,19 +579,42 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     int64_t groups = 512 / jgroups;
     if (groups > a.items) groups = a.items;
     if (groups < 1) groups = 1;
-    const dim3 grid{unsigned(groups), unsigned(jgroups), 1u};
-    const size_t shm = size_t(12 * p.npad * p.npad);
     const int suf = M - i;
+    if (p.npad <= 64) {
+        const dim3 grid{unsigned(groups), unsigned(jgroups), 1u};
+        const size_t shm = size_t(12 * p.npad * p.npad);
 #define NPF_STAGE_CASE(NP_, S_)                                                           \
     if (p.npad == NP_ && suf == S_) {                                                    \
         set_lds_limit(stage_bf3<NP_, S_>, int(shm));                                      \
         hipLaunchKernelGGL((stage_bf3<NP_, S_>), grid, dim3(kThreads), shm, ca.stream, a); \
         return hipGetLastError();                                                         \
     }
-    NPF_STAGE_CASE(32, 1) NPF_STAGE_CASE(32, 2) NPF_STAGE_CASE(32, 3)
-    NPF_STAGE_CASE(64, 1) NPF_STAGE_CASE(64, 2) NPF_STAGE_CASE(64, 3)
+        NPF_STAGE_CASE(32, 1) NPF_STAGE_CASE(32, 2) NPF_STAGE_CASE(32, 3)
+        NPF_STAGE_CASE(64, 1) NPF_STAGE_CASE(64, 2) NPF_STAGE_CASE(64, 3)
 #undef NPF_STAGE_CASE
+        return hipErrorInvalidValue;
+    }
+#define NPF_STAGE_TR(NP_, S_, TT_)                                                         \
+    if (p.npad == NP_ && suf == S_) {                                                      \
+        const dim3 grid{unsigned(groups), unsigned(jgroups), unsigned((NP_ / 16 + TT_ - 1) / TT_)}; \
+        const size_t shm = size_t(12 * NP_ * TT_ * 16);                                    \
+        set_lds_limit(stage_bf3_tr<NP_, S_, TT_>, int(shm));                                \
+        hipLaunchKernelGGL((stage_bf3_tr<NP_, S_, TT_>), grid, dim3(kThreads), shm, ca.stream, a); \
+        return hipGetLastError();                                                           \
+    }
+    NPF_STAGE_TR(96, 1, 3) NPF_STAGE_TR(96, 2, 3) NPF_STAGE_TR(96, 3, 3)
+    NPF_STAGE_TR(128, 1, 4) NPF_STAGE_TR(128, 2, 4) NPF_STAGE_TR(128, 3, 4)
+    NPF_STAGE_TR(160, 1, 2) NPF_STAGE_TR(160, 2, 2) NPF_STAGE_TR(160, 3, 2)
+    NPF_STAGE_TR(192, 1, 2) NPF_STAGE_TR(192, 2, 2) NPF_STAGE_TR(192, 3, 2)
+    NPF_STAGE_TR(224, 1, 2) NPF_STAGE_TR(224, 2, 2) NPF_STAGE_TR(224, 3, 2)
+    NPF_STAGE_TR(256, 1, 2) NPF_STAGE_TR(256, 2, 2) NPF_STAGE_TR(256, 3, 2)
+#undef NPF_STAGE_TR
     return hipErrorInvalidValue;
+}
+
+bool bf3_stage_supported(const npf_plan_s *p)
+{
+    return p->prec == NPF_BF16X3 && p->N <= 4;
 }
 
 }  // namespace npf

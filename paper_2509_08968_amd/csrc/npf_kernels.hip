@@ -242,6 +242,7 @@ hipError_t launch_psi_a(const ChainArgs &a)
     const int64_t UM = p.U[a.M];
     char *dst = a.ws + p.lay.buf[0];
     const double2 *Psi = reinterpret_cast<const double2 *>(a.U);
+    if (a.A->kind == NPF_SRC_DENSE && psi_a_mfma_supported(&p)) return launch_psi_a_mfma(a);
     if (a.A->kind == NPF_SRC_DENSE) {
         if (p.prec == NPF_FP64)
             hipLaunchKernelGGL((psi_a_dense<double2, double>), dim3(grid_for(UM * p.Jpad)),

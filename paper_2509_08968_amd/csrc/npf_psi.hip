@@ -1,0 +1,124 @@
+// Upper-index contraction on MFMA for dense derivative tensors (Alg. 2 step 4, done
+// first):  T_0[r][jj] = sum_k A_M[k][r] Psi[j0 + jj][k]  for every sorted tuple r.
+// A_M is real and read once per output-mode block, so the kernel is bound by the HBM
+// stream of A_M; Psi^T for the block (n x Jpad complex) stays in LDS for the whole launch
+// and each workgroup sweeps 64-row tiles of r.  FP64 MFMA for the FP64 path, FP32 MFMA
+// (FP32 accumulation) for the FP32 and split-BF16 paths.
+#include "npf_device.h"
+#include "npf_internal.h"
+#include "npf_mfma.h"
+
+namespace npf {
+
+namespace {
+
+constexpr int kThreads = 256;   // 4 waves, 16 rows r each
+
+template <Eng E, int NJT>
+__global__ void __launch_bounds__(kThreads)
+psi_a_mfma(const double *__restrict__ A, const double2 *__restrict__ Psi, int64_t n, int64_t UM,
+           int64_t j0, int64_t J, int64_t Jpad, void *__restrict__ out_)
+{
+    using T = EngT<E>;
+    using acc_t = typename T::acc;
+    using real = typename T::real;
+    using cplx = typename T::cplx;
+    extern __shared__ __align__(16) char lds[];
+    cplx *L = reinterpret_cast<cplx *>(lds);         // Psi^T[k][jj], zero for jj >= J
+    const int64_t npad32 = (n + 31) / 32 * 32;
+    for (int64_t x = threadIdx.x; x < npad32 * Jpad; x += blockDim.x) {
+        const int64_t k = x / Jpad, jj = x % Jpad;
+        double2 v = make_double2(0.0, 0.0);
+        if (k < n && jj < J) v = Psi[(j0 + jj) * n + k];
+        L[x] = cplx{real(v.x), real(v.y)};
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    cplx *out = static_cast<cplx *>(out_);
+    for (int64_t r0 = int64_t(blockIdx.x) * 64 + wave * 16; r0 < UM; r0 += int64_t(gridDim.x) * 64) {
+        const int64_t r = r0 + c;
+        const bool r_ok = r < UM;
+        acc_t ar[NJT], ai[NJT];
+#pragma unroll
+        for (int u = 0; u < NJT; ++u) ar[u] = ai[u] = acc_t{0, 0, 0, 0};
+        for (int64_t k0 = 0; k0 < npad32; k0 += 32) {
+            // A operand: A^T[r][k] = A[k][r] (lanes of a group read consecutive r); the
+            // eight loads of a 32-wide chunk are issued together.
+            real av[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t k = k0 + 4 * q + g;
+                av[q] = (r_ok && k < n) ? real(A[k * UM + r]) : real(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t k = k0 + 4 * q + g;
+#pragma unroll
+                for (int u = 0; u < NJT; ++u) {
+                    const cplx p = L[k * Jpad + u * 16 + c];      // B operand: Psi^T[k][jj]
+                    ar[u] = mfma(av[q], p.x, ar[u]);
+                    ai[u] = mfma(av[q], p.y, ai[u]);
+                }
+            }
+        }
+        // D[row = r0 + out_row][col = jj]: lanes of a group write consecutive jj.
+#pragma unroll
+        for (int u = 0; u < NJT; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t rr = r0 + out_row<E>(q, g);
+                if (rr < UM) out[rr * Jpad + u * 16 + c] = cplx{ar[u][q], ai[u][q]};
+            }
+    }
+}
+
+template <Eng E, int NJT>
+hipError_t launch(const double *A, const double2 *Psi, int64_t n, int64_t UM, int64_t j0, int64_t J,
+                  int64_t Jpad, void *out, hipStream_t s)
+{
+    const int64_t npad32 = (n + 31) / 32 * 32;
+    const size_t shm = size_t(npad32 * Jpad) * sizeof(typename EngT<E>::cplx);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&psi_a_mfma<E, NJT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+    int64_t tiles = (UM + 63) / 64;
+    if (tiles > 1024) tiles = 1024;
+    hipLaunchKernelGGL((psi_a_mfma<E, NJT>), dim3(unsigned(tiles)), dim3(kThreads), shm, s, A, Psi,
+                       n, UM, j0, J, Jpad, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool psi_a_mfma_supported(const npf_plan_s *p)
+{
+    // Psi^T of the block must fit in LDS and the block must be at most 128 modes.
+    const int64_t npad32 = (p->n + 31) / 32 * 32;
+    const int64_t bytes = npad32 * p->Jpad * (p->prec == NPF_FP64 ? 16 : 8);
+    return p->Jpad <= 128 && bytes <= 144 * 1024;
+}
+
+hipError_t launch_psi_a_mfma(const ChainArgs &a)
+{
+    const npf_plan_s &p = *a.plan;
+    const int64_t UM = p.U[a.M];
+    void *dst = a.ws + p.lay.buf[0];
+    const double2 *Psi = reinterpret_cast<const double2 *>(a.U);
+    const int njt = int(p.Jpad / 16);
+#define NPF_PSI_CASE(E_, K_)                                                                \
+    if (njt == K_) return launch<E_, K_>(a.A->values, Psi, p.n, UM, a.j0, a.J, p.Jpad, dst, \
+                                         a.stream);
+    if (p.prec == NPF_FP64) {
+        NPF_PSI_CASE(Eng::F64, 1) NPF_PSI_CASE(Eng::F64, 2) NPF_PSI_CASE(Eng::F64, 3)
+        NPF_PSI_CASE(Eng::F64, 4) NPF_PSI_CASE(Eng::F64, 5) NPF_PSI_CASE(Eng::F64, 6)
+        NPF_PSI_CASE(Eng::F64, 7) NPF_PSI_CASE(Eng::F64, 8)
+    } else {
+        NPF_PSI_CASE(Eng::F32, 1) NPF_PSI_CASE(Eng::F32, 2) NPF_PSI_CASE(Eng::F32, 3)
+        NPF_PSI_CASE(Eng::F32, 4) NPF_PSI_CASE(Eng::F32, 5) NPF_PSI_CASE(Eng::F32, 6)
+        NPF_PSI_CASE(Eng::F32, 7) NPF_PSI_CASE(Eng::F32, 8)
+    }
+#undef NPF_PSI_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace npf

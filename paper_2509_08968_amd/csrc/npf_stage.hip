@@ -198,7 +198,7 @@ bool stage_mfma_supported(const npf_plan_s *p) { return p->n <= kMaxN; }
 hipError_t launch_stage_mfma(const ChainArgs &ca, int i)
 {
     const npf_plan_s &p = *ca.plan;
-    if (bf3_small_supported(&p)) return launch_stage_bf3(ca, i);
+    if (bf3_stage_supported(&p)) return launch_stage_bf3(ca, i);
     const int M = ca.M;
     const uint64_t *tt = reinterpret_cast<const uint64_t *>(ca.ws + p.lay.ttab);
     StageArgs sa;
