@@ -50,6 +50,31 @@ def reference_modes(s):
     return sorted({int(np.argmin(d2.min(1))), 5})
 
 
+def kernel_source_digest():
+    """Digest of the HIP sources: counter summaries are valid only for the kernels they were
+    taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2509_08968_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<workload>_<precision>.json), or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_digest") != kernel_source_digest():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
 def kernel_work(name, sysm, plan):
     """(algorithmic flops, algorithmic HBM bytes, bound, uses MFMA) of ONE launch of a
     kernel, from the shapes (a complex multiply-add counts 8 flops, real x complex 4)."""
@@ -185,6 +210,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -204,6 +231,12 @@ def main():
     device = "cuda:0"
     torch.cuda.set_device(0)
     B.lib()
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s = I.WORKLOADS[args.workload]()
     sysm = B.upload_system(s, device)
     log(f"[bench] workload {args.workload}: n={s.n} orders={s.orders}")
@@ -251,7 +284,9 @@ def main():
             peak = (PEAK_TFLOPS if mfma else PEAK_VALU_TFLOPS)[args.precision]
             unit = "TFLOP/s"
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "kernel": name,
+                "frac": achieved / peak,
+                "traffic": measured_traffic(args.workload, args.precision, name),
+                "algorithmic_bytes": byts, "kernel": name,
                 "avg_launch_ms": tot / cnt, "launches_per_step": cnt / args.steps,
                 "share_of_step": tot / args.steps / res["ms_per_step"],
                 "timing": "HIP events around every launch, eager pass of the same steps"}

@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 output for the benchmark workloads (host only, no GPU).
+
+Turns the CSV files of `rocprofv3 --kernel-trace --stats` and of two `rocprofv3 --pmc`
+passes (FETCH_SIZE, then WRITE_SIZE) into short text summaries and a JSON file with the
+HBM bytes per launch of every kernel of one step, which bench.py reports as
+roofline.traffic while the kernel sources are unchanged.
+
+Counter scaling: bench.py --copy-probe-mib X runs one device copy of X MiB before the
+workload; the factor that maps that copy's FETCH_SIZE (resp. WRITE_SIZE) to X MiB is
+applied to every dispatch.  Dispatches are named by the launch order of npf_run, which is
+fixed for a plan: prepare; per order M and mode block: the upper-index contraction (two
+launches for sparse tensors: clear + scatter), stages 1..M-1, the fused last stage, two
+partial-sum launches; finalize.
+
+usage: python -m paper_2509_08968_amd.counters WORKLOAD PRECISION FETCH_CSV WRITE_CSV
+           COPY_MIB TRACE_STATS_CSV OUT_DIR "COMMAND TEXT"
+"""
+from __future__ import annotations
+
+import csv
+import json
+import os
+import sys
+from collections import defaultdict
+
+
+def launch_names(workload: str, precision: str, budget: int = 0):
+    """Kernel names of one npf_run step, in dispatch order."""
+    from . import binding as B
+    from . import inputs as I
+    s = I.WORKLOADS[workload]()
+    plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget)
+    names = ["prepare"]
+    for M in range(2, s.order_max + 1):
+        sparse = s.support.get(M) is not None
+        for _ in range(plan.n_blocks):
+            if sparse:
+                names += [f"o{M}_psi_a.clear", f"o{M}_psi_a"]
+            else:
+                names.append(f"o{M}_psi_a")
+            names += [f"o{M}_stage{i}" for i in range(1, M)]
+            names += [f"o{M}_fused", f"o{M}_reduce.l1", f"o{M}_reduce.l2"]
+    names.append("finalize")
+    plan.close()
+    return names
+
+
+def _dispatches(path):
+    rows = list(csv.DictReader(open(path)))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+
+
+def _scale(disp, copy_mib):
+    copies = [v for k, v in disp if k.startswith("__amd_rocclr_copyBuffer")]
+    big = max(copies)
+    return (copy_mib * 1024.0) / big            # counters are in KiB
+
+
+def traffic(workload, precision, fetch_csv, write_csv, copy_mib, budget=0):
+    names = launch_names(workload, precision, budget)
+    out = {}
+    for ctr, path in (("fetch", fetch_csv), ("write", write_csv)):
+        disp = _dispatches(path)
+        f = _scale(disp, copy_mib)
+        lib = [(k, v) for k, v in disp if "npf::" in k]
+        steps = len(lib) // len(names)
+        acc = defaultdict(list)
+        for s in range(steps):
+            for i, nm in enumerate(names):
+                k, v = lib[s * len(names) + i]
+                acc[nm].append((k, v * f * 1024.0))
+        for nm, vals in acc.items():
+            d = out.setdefault(nm, {"symbol": vals[0][0][:100]})
+            blocks = names.count(nm)
+            d[f"{ctr}_bytes_per_launch"] = sum(v for _, v in vals) / len(vals)
+            d[f"{ctr}_scale"] = f
+            d["launches_per_step"] = blocks
+    for d in out.values():
+        d["bytes_per_launch"] = d.get("fetch_bytes_per_launch", 0.0) + d.get("write_bytes_per_launch", 0.0)
+    return out
+
+
+def main(argv):
+    workload, precision, fetch_csv, write_csv, copy_mib, stats_csv, out_dir, cmd = argv[:8]
+    budget = {"n128-o4-dense-resonant": 64 << 30}.get(workload, 0)
+    t = traffic(workload, precision, fetch_csv, write_csv, float(copy_mib), budget)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    js = {"workload": workload, "precision": precision,
+          "source_digest": bench.kernel_source_digest(), "kernels": t,
+          "note": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled "
+                  "by the ratio of a device copy of known size to what the counter reports "
+                  "for it; valid for the kernel sources with this digest"}
+    with open(os.path.join(out_dir, f"traffic_{workload}_{precision}.json"), "w") as f:
+        json.dump(js, f, indent=1)
+    lines = [f"# HBM traffic per launch, {workload}, {precision}",
+             f"# commands (repo root, TMPDIR=/tmp):", *[f"#   {c}" for c in cmd.split(" ;; ")],
+             f"# counter scale factors (copy of {copy_mib} MiB): fetch "
+             f"{next(iter(t.values()))['fetch_scale']:.3f}, write {next(iter(t.values()))['write_scale']:.3f}",
+             "# kernel  launches/step  fetch_GB  write_GB  symbol"]
+    for nm, d in sorted(t.items(), key=lambda kv: -kv[1]["bytes_per_launch"]):
+        lines.append(f"{nm:18s} {d['launches_per_step']:3d} {d['fetch_bytes_per_launch'] / 1e9:10.4f} "
+                     f"{d['write_bytes_per_launch'] / 1e9:10.4f}  {d['symbol']}")
+    with open(os.path.join(out_dir, f"hbm_traffic_{workload}_{precision}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# rocprofv3 kernel-trace statistics, {workload}, {precision}",
+             "# command (repo root, TMPDIR=/tmp):", f"#   {cmd.split(' ;; ')[0]}",
+             "# calls  total_ms  avg_us  min_us  max_us  pct  kernel"]
+    for r in rows:
+        lines.append(f"{int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
+                     f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}  {r['Name'][:100]}")
+    with open(os.path.join(out_dir, f"kernel_trace_{workload}_{precision}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

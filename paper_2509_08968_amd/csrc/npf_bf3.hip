@@ -4,6 +4,8 @@
 // Khatri-Rao factor, the eigenvalues) lives in LDS for the whole launch; the grid is a
 // few workgroups per CU that sweep the items, and the right operand rows of the next item
 // are loaded into registers while the current item computes.
+#include <type_traits>
+
 #include "npf_device.h"
 #include "npf_internal.h"
 #include "npf_mfma.h"
@@ -256,6 +258,220 @@ fused_bf3(Bf3Args a)
     }
 }
 
+// ------------------------------------------------------------------ fused last stage, n > 64
+// Same arithmetic as fused_bf3; a workgroup owns one 32-wide t-slice (grid.z) of every
+// item: the slices of Phi^T and zeta live in LDS, the reduction runs over the slice's t
+// only, and the partial P of each (item group, slice) workgroup is summed with the others
+// in the fixed-order partial sums (P is linear in the sum over t).
+template <int NP, int M>
+__global__ void __launch_bounds__(kThreads)
+fused_bf3_tr(Bf3Args a)
+{
+    constexpr int NKT = NP / 16, KC = NP / 32, AG = NP / 8, N2 = NP * NP;
+    constexpr int PLP = NP * 32;     // elements per LDS plane of the Phi^T slice
+    constexpr int PLZ = 32 * NP;     // elements per LDS plane of the zeta slice
+    extern __shared__ __align__(16) char lds[];
+    __bf16 *Lphi = reinterpret_cast<__bf16 *>(lds);
+    __bf16 *Lz = reinterpret_cast<__bf16 *>(lds + 12 * PLP);
+    double2 *Llam = reinterpret_cast<double2 *>(lds + 12 * PLP + 12 * PLZ);
+    const int slice = int(blockIdx.z), t_base = slice * 32;
+    {
+        const int4 *gp = reinterpret_cast<const int4 *>(a.phiE);
+        int4 *lp = reinterpret_cast<int4 *>(Lphi);
+        for (int x = threadIdx.x; x < 6 * AG * 32; x += blockDim.x) {
+            const int tl = x % 32, ag = (x / 32) % AG, pl = x / (32 * AG);
+            lp[x] = gp[(int64_t(pl) * AG + ag) * NP + t_base + tl];
+        }
+        // zeta planes are in fragment order: the 32-row chunk of this slice is contiguous.
+        const int4 *gz = reinterpret_cast<const int4 *>(a.zetaE);
+        int4 *lz = reinterpret_cast<int4 *>(Lz);
+        for (int x = threadIdx.x; x < 6 * 4 * NP; x += blockDim.x) {
+            const int within = x % (4 * NP), pl = x / (4 * NP);
+            lz[x] = gz[int64_t(pl) * (N2 / 8) + int64_t(slice) * 4 * NP + within];
+        }
+        for (int t = threadIdx.x; t < NP; t += blockDim.x)
+            Llam[t] = t < a.n ? a.lam[t] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
+    const bool wave_on = jw < a.Jpad;
+    const int64_t jl = jw + c;
+    const bool j_ok = wave_on && jl < a.J;
+    const double2 lam_j = j_ok ? Llam[a.j0 + jl] : make_double2(0.0, 0.0);
+    const float guard = fmaxf(float(a.tau2), float(4.0 * a.eps * a.eps));
+    const int nn = int(a.n), jp = int(a.Jpad);
+
+    double pacc_r[NKT][4], pacc_i[NKT][4];
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pacc_r[kt][r] = pacc_i[kt][r] = 0.0;
+
+    const float2 *X = static_cast<const float2 *>(a.X);
+    auto load_chunk = [&](int64_t it, int kc, float2 (&dst)[8]) {
+        const float2 *Xp = X + it * a.n * a.Jpad + jw + c;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int ar = kc * 32 + 8 * g + s;
+            dst[s] = ar < nn ? Xp[ar * jp] : make_float2(0.f, 0.f);
+        }
+    };
+    auto last_of = [&](uint64_t pk) { return int((pk >> (8 * (M - 2))) & 0xff); };
+    // The slice has work for an item when some t in it is >= last(p).
+    auto active = [&](uint64_t pk) { return t_base + 32 > last_of(pk); };
+
+    int64_t it = blockIdx.x;
+    uint64_t pk = (it < a.items) ? a.ptab[it] : 0;
+    float2 cur[8];
+    if (wave_on && it < a.items && active(pk)) load_chunk(it, 0, cur);
+    if (wave_on)
+    for (; it < a.items; it += gridDim.x) {
+        const int64_t itn = it + gridDim.x;
+        const uint64_t pkn = (itn < a.items) ? a.ptab[itn] : 0;
+        const bool next_on = itn < a.items && active(pkn);
+        if (!active(pk)) {
+            if (next_on) load_chunk(itn, 0, cur);
+            pk = pkn;
+            continue;
+        }
+        int32_t p[M - 1];
+#pragma unroll
+        for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
+        double2 lam_p = Llam[p[0]];
+        double den = 1.0;
+        int run = 1;
+#pragma unroll
+        for (int q = 1; q < M - 1; ++q) {
+            lam_p = add_fp64(lam_p, Llam[p[q]]);
+            if (p[q] == p[q - 1]) {
+                ++run;
+                den *= double(run);
+            } else {
+                run = 1;
+            }
+        }
+        const int m = p[M - 2];
+        const double w_gt = -1.0 / den, w_eq = -1.0 / (den * double(run + 1));
+        const float w_gt_f = float(w_gt), w_eq_f = float(w_eq);
+        // zp[k] = prod_i zeta[p_i][k] (FP32), loaded now and used after the products.
+        float2 zp[NKT];
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+            const int k = kt * 16 + c;
+            float2 z = a.zeta32[p[0] * NP + k];
+#pragma unroll
+            for (int q = 1; q < M - 1; ++q) {
+                const float2 w = a.zeta32[p[q] * NP + k];
+                z = make_float2(z.x * w.x - z.y * w.y, z.x * w.y + z.y * w.x);
+            }
+            zp[kt] = z;
+        }
+
+        // GEMM1 over the slice's two t-tiles, rows loaded one K-chunk ahead.
+        v4f sr[2], si[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) sr[u] = si[u] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            float2 nxt[8];
+            if (kc + 1 < KC) load_chunk(it, kc + 1, nxt);
+            else if (next_on) load_chunk(itn, 0, nxt);
+            Split3 xr, xi;
+            split_x(cur, xr, xi);
+            const Split3 xng = negx3(xi);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int pidx = ((kc * 4 + g) * 32 + 16 * u + c) * 8;
+                Split3 pr, pi;
+                pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PLP + pidx);
+                pr.m = *reinterpret_cast<const v8bf *>(Lphi + 1 * PLP + pidx);
+                pr.l = *reinterpret_cast<const v8bf *>(Lphi + 2 * PLP + pidx);
+                pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PLP + pidx);
+                pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PLP + pidx);
+                pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PLP + pidx);
+                sr[u] = mm6(pr, xr, sr[u]);
+                sr[u] = mm6(pi, xng, sr[u]);
+                si[u] = mm6(pr, xi, si[u]);
+                si[u] = mm6(pi, xr, si[u]);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+        }
+        // Divisor (FP64) and division into the reduction's A operand.
+        float hre[8], him[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+            const int u = s8 >> 2, r = s8 & 3;
+            const int t = t_base + 16 * u + 4 * g + r;
+            float vr = 0.f, vi = 0.f;
+            if (j_ok && t >= m && t < nn) {
+                const double2 acc = add_fp64(lam_p, Llam[t]);
+                const double2 d = make_double2(acc.x - lam_j.x, acc.y - lam_j.y);
+                const float dx = float(d.x), dy = float(d.y);
+                const float dd = dx * dx + dy * dy;
+                const float w = (t == m) ? w_eq_f : w_gt_f;
+                const float sx = sr[u][r], sy = si[u][r];
+                if (dd < guard) {
+                    const double2 dc = divisor_fp64(acc, lam_j, a.eps);
+                    const double f = ((t == m) ? w_eq : w_gt) / (dc.x * dc.x + dc.y * dc.y);
+                    vr = float((double(sx) * dc.x + double(sy) * dc.y) * f);
+                    vi = float((double(sy) * dc.x - double(sx) * dc.y) * f);
+                } else {
+                    float rc = __builtin_amdgcn_rcpf(dd);
+                    rc = rc * (2.0f - dd * rc);
+                    const float f = w * rc;
+                    vr = (sx * dx + sy * dy) * f;
+                    vi = (sy * dx - sx * dy) * f;
+                }
+            }
+            hre[s8] = vr;
+            him[s8] = vi;
+        }
+        const Split3 ar_ = split8(hre), ai_ = split8(him);
+        const Split3 an_ = negx3(ai_);
+        // GEMM2 over the slice (K = 32 t) for every k tile, then P += zp * R in FP64.
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+            const int z0 = (g * NP + kt * 16 + c) * 8;
+            Split3 zr_, zi_;
+            zr_.h = *reinterpret_cast<const v8bf *>(Lz + 0 * PLZ + z0);
+            zr_.m = *reinterpret_cast<const v8bf *>(Lz + 1 * PLZ + z0);
+            zr_.l = *reinterpret_cast<const v8bf *>(Lz + 2 * PLZ + z0);
+            zi_.h = *reinterpret_cast<const v8bf *>(Lz + 3 * PLZ + z0);
+            zi_.m = *reinterpret_cast<const v8bf *>(Lz + 4 * PLZ + z0);
+            zi_.l = *reinterpret_cast<const v8bf *>(Lz + 5 * PLZ + z0);
+            v4f rr = v4f{0, 0, 0, 0}, ri = v4f{0, 0, 0, 0};
+            rr = mm6(ar_, zr_, rr);
+            rr = mm6(an_, zi_, rr);
+            ri = mm6(ar_, zi_, ri);
+            ri = mm6(ai_, zr_, ri);
+            const float2 z = zp[kt];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float vr = rr[r], vi = ri[r];
+                pacc_r[kt][r] += double(vr * z.x - vi * z.y);
+                pacc_i[kt][r] += double(vr * z.y + vi * z.x);
+            }
+        }
+        pk = pkn;
+    }
+    if (!wave_on) return;
+    double2 *dst = a.parts + (int64_t(blockIdx.z) * gridDim.x + blockIdx.x) * a.Jpad * a.n;
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) {
+        const int64_t k = kt * 16 + c;
+        if (k >= a.n) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t j = jw + 4 * g + r;
+            dst[j * a.n + k] = make_double2(pacc_r[kt][r], pacc_i[kt][r]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ one chain stage
 template <int NP, int SUF>
 __global__ void __launch_bounds__(kThreads)
@@ -460,34 +676,43 @@ stage_bf3_tr(Bf3Args a)
         }
         const int tt0 = (m > t_base) ? (m - t_base) / 16 : 0;
         v4f sr[TT], si[TT];
+        // Straight-line tile loops for each first active tile (no branches between MFMAs).
+        auto sweep = [&](auto first) {
+            constexpr int T0 = decltype(first)::value;
 #pragma unroll
-        for (int tt = 0; tt < TT; ++tt) sr[tt] = si[tt] = v4f{0, 0, 0, 0};
+            for (int tt = 0; tt < TT; ++tt) sr[tt] = si[tt] = v4f{0, 0, 0, 0};
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            float2 nxt[8];
-            if (kc + 1 < KC) load_chunk(it, buf, kc + 1, nxt);
-            else if (next_on) load_chunk(itn, nbuf, 0, nxt);
-            Split3 xr, xi;
-            split_x(cur, xr, xi);
-            const Split3 xng = negx3(xi);
+            for (int kc = 0; kc < KC; ++kc) {
+                float2 nxt[8];
+                if (kc + 1 < KC) load_chunk(it, buf, kc + 1, nxt);
+                else if (next_on) load_chunk(itn, nbuf, 0, nxt);
+                Split3 xr, xi;
+                split_x(cur, xr, xi);
+                const Split3 xng = negx3(xi);
 #pragma unroll
-            for (int tt = 0; tt < TT; ++tt) {
-                if (tt < tt0) continue;
-                const int pidx = ((kc * 4 + g) * TW + tt * 16 + c) * 8;
-                Split3 pr, pi;
-                pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PL + pidx);
-                pr.m = *reinterpret_cast<const v8bf *>(Lphi + 1 * PL + pidx);
-                pr.l = *reinterpret_cast<const v8bf *>(Lphi + 2 * PL + pidx);
-                pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PL + pidx);
-                pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PL + pidx);
-                pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PL + pidx);
-                sr[tt] = mm6(pr, xr, sr[tt]);
-                sr[tt] = mm6(pi, xng, sr[tt]);
-                si[tt] = mm6(pr, xi, si[tt]);
-                si[tt] = mm6(pi, xr, si[tt]);
+                for (int tt = T0; tt < TT; ++tt) {
+                    const int pidx = ((kc * 4 + g) * TW + tt * 16 + c) * 8;
+                    Split3 pr, pi;
+                    pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PL + pidx);
+                    pr.m = *reinterpret_cast<const v8bf *>(Lphi + 1 * PL + pidx);
+                    pr.l = *reinterpret_cast<const v8bf *>(Lphi + 2 * PL + pidx);
+                    pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PL + pidx);
+                    pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PL + pidx);
+                    pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PL + pidx);
+                    sr[tt] = mm6(pr, xr, sr[tt]);
+                    sr[tt] = mm6(pi, xng, sr[tt]);
+                    si[tt] = mm6(pr, xi, si[tt]);
+                    si[tt] = mm6(pi, xr, si[tt]);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
             }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+        };
+        switch (tt0) {
+        case 0: sweep(std::integral_constant<int, 0>{}); break;
+        case 1: if constexpr (TT > 1) sweep(std::integral_constant<int, (TT > 1 ? 1 : 0)>{}); break;
+        case 2: if constexpr (TT > 2) sweep(std::integral_constant<int, (TT > 2 ? 2 : 0)>{}); break;
+        default: if constexpr (TT > 3) sweep(std::integral_constant<int, (TT > 3 ? 3 : 0)>{}); break;
         }
         const int64_t rp = it / a.U_suf, rs = it % a.U_suf;
         float2 *dst = static_cast<float2 *>(a.out) + (rp * a.U_suf + rs) * a.Jpad + jw + c;
@@ -558,6 +783,40 @@ hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, c
     NPF_FUSED_CASE(64, 2) NPF_FUSED_CASE(64, 3) NPF_FUSED_CASE(64, 4)
 #undef NPF_FUSED_CASE
     return hipErrorInvalidValue;
+}
+
+// Partial slots written by the fused split-BF16 kernel for n > 64: groups x slices.
+int64_t fused_bf3_tr_slices(const npf_plan_s *p) { return p->npad / 32; }
+
+hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J,
+                               const double *lam, char *ws, int64_t groups, hipStream_t s)
+{
+    Bf3Args a = base_args(p, ws, lam);
+    a.X = ws + p->lay.buf[(M - 1) % 2];
+    a.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
+    a.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
+    a.J = J;
+    a.j0 = j0;
+    a.items = p->U[M - 1];
+    a.M = M;
+    const int NP = int(p->npad);
+    const dim3 grid{unsigned(groups), unsigned((p->Jpad + 63) / 64), unsigned(NP / 32)};
+    const size_t shm = size_t(24 * NP * 32 + 16 * NP);
+#define NPF_FUSED_TR(NP_, M_)                                                                 \
+    if (NP == NP_ && M == M_) {                                                              \
+        set_lds_limit(fused_bf3_tr<NP_, M_>, int(shm));                                       \
+        hipLaunchKernelGGL((fused_bf3_tr<NP_, M_>), grid, dim3(kThreads), shm, s, a);         \
+        return hipGetLastError();                                                             \
+    }
+    NPF_FUSED_TR(96, 2) NPF_FUSED_TR(96, 3) NPF_FUSED_TR(96, 4)
+    NPF_FUSED_TR(128, 2) NPF_FUSED_TR(128, 3) NPF_FUSED_TR(128, 4)
+#undef NPF_FUSED_TR
+    return hipErrorInvalidValue;
+}
+
+bool bf3_tr_fused_supported(const npf_plan_s *p)
+{
+    return p->prec == NPF_BF16X3 && (p->npad == 96 || p->npad == 128) && p->N <= 4;
 }
 
 hipError_t launch_stage_bf3(const ChainArgs &ca, int i)

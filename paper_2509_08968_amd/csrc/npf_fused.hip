@@ -477,13 +477,20 @@ hipError_t launch_fused_eng(const FusedArgs &fa, int nkt, int64_t groups, hipStr
 
 }  // namespace
 
-int64_t fused_groups(const npf_plan_s *p, int M)
+// Workgroups along the items of the fused kernel (grid.x).
+static int64_t fused_gx(const npf_plan_s *p, int M)
 {
     const int64_t items = p->U[M - 1];
     const int64_t jgroups = (p->Jpad + 63) / 64;
-    int64_t g = (bf3_small_supported(p) ? 256 : 512) / jgroups;
+    int64_t g = (bf3_small_supported(p) ? 256 : (bf3_tr_fused_supported(p) ? 128 : 512)) / jgroups;
     if (g < 1) g = 1;
     return items < g ? items : g;
+}
+
+// Partial-P slots written by the fused kernel for order M.
+int64_t fused_groups(const npf_plan_s *p, int M)
+{
+    return fused_gx(p, M) * (bf3_tr_fused_supported(p) ? fused_bf3_tr_slices(p) : 1);
 }
 
 hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V, char *ws,
@@ -525,8 +532,9 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
     fa.eps = p->prob.eps;
     fa.tau2 = p->prob.tau * p->prob.tau;
     const int nkt = int(p->npad / 16);
-    const int64_t groups = fused_groups(p, M);
+    const int64_t groups = fused_gx(p, M);
     if (bf3_small_supported(p)) return launch_fused_bf3(p, M, j0, J, lam, ws, groups, s);
+    if (bf3_tr_fused_supported(p)) return launch_fused_bf3_tr(p, M, j0, J, lam, ws, groups, s);
     switch (p->prec) {
     case NPF_FP64: return launch_fused_eng<Eng::F64>(fa, nkt, groups, s);
     case NPF_FP32: return launch_fused_eng<Eng::F32>(fa, nkt, groups, s);

@@ -136,6 +136,10 @@ bool bf3_small_supported(const npf_plan_s *p);
 hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
                             char *ws, int64_t groups, hipStream_t s);
 hipError_t launch_stage_bf3(const ChainArgs &a, int i);
+bool bf3_tr_fused_supported(const npf_plan_s *p);
+int64_t fused_bf3_tr_slices(const npf_plan_s *p);
+hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J,
+                               const double *lam, char *ws, int64_t groups, hipStream_t s);
 bool bf3_stage_supported(const npf_plan_s *p);
 // MFMA upper-index contraction for dense tensors.
 bool psi_a_mfma_supported(const npf_plan_s *p);
