@@ -34,8 +34,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Workspace cap per workload (the memory limit of Alg. 1, applied to HBM); 0 = none.
-WORKLOAD_BUDGET = {"n128-o4-dense-resonant": 64 << 30}
+# Workspace cap per workload and precision (the memory limit of Alg. 1, applied to HBM);
+# 0 = none.  The n=200 workload needs 16-mode blocks of 5.4 GB (FP32 operands) or 10.8 GB
+# (FP64) per mode.
+WORKLOAD_BUDGET = {"n128-o4-dense-resonant": {"*": 64 << 30},
+                   "n200-o4-dense-hash": {"*": 96 << 30, "fp64": 192 << 30}}
+
+
+def budget_for(workload, precision):
+    b = WORKLOAD_BUDGET.get(workload, {})
+    return b.get(precision, b.get("*", 0))
+
+
+# Workloads whose oracle reference is stored (the oracle takes minutes per mode there).
+STORED_REFERENCE = {"n200-o4-dense-hash": os.path.join(ROOT, "tests", "golden",
+                                                       "hash200_modes.json")}
 
 
 def reference_modes(s):
@@ -85,6 +98,8 @@ def kernel_work(name, sysm, plan):
     what = name.split("_", 1)[1]
     if what == "psi_a":
         t = sysm.tensors[M - 2]
+        if t.kind == 2:                      # generated on the device: no A traffic
+            return 4.0 * n * J * U[M], 8.0 * J * U[M], "alu", False
         if t.kind == 1:
             nnz = int(t.desc.nnz)
             return 4.0 * nnz * J, 8.0 * nnz + 8.0 * J * U[M], "alu", False
@@ -243,10 +258,17 @@ def main():
 
     # Oracle reference (outside every timed region): P rows and NPF columns of the modes.
     t0 = time.perf_counter()
-    modes = reference_modes(s)
-    refP = {M: oracle.sym(s, M, modes=modes)["P"] for M in s.orders}
-    zeta = s.delta * s.U[modes, :]
-    ref_npf = s.V[:, modes] * (zeta + sum(refP.values())).T
+    if args.workload in STORED_REFERENCE:
+        g = json.load(open(STORED_REFERENCE[args.workload]))
+        cplx = lambda a: np.asarray(a)[..., 0] + 1j * np.asarray(a)[..., 1]
+        modes = g["modes"]
+        refP = {M: cplx(g["P"][str(M)]) for M in s.orders}
+        ref_npf = cplx(g["npf_columns"]).T
+    else:
+        modes = reference_modes(s)
+        refP = {M: oracle.sym(s, M, modes=modes)["P"] for M in s.orders}
+        zeta = s.delta * s.U[modes, :]
+        ref_npf = s.V[:, modes] * (zeta + sum(refP.values())).T
     log(f"[bench] oracle reference ({len(modes)} modes) in {time.perf_counter() - t0:.1f} s")
 
     def errors(r):
@@ -254,9 +276,8 @@ def main():
         e["npf"] = rel(r["npf"][:, modes], ref_npf)
         return e
 
-    budget = WORKLOAD_BUDGET.get(args.workload, 0)
     res = time_path(sysm, s, args.precision, args.steps, args.warmup, device,
-                    not args.no_profile, budget)
+                    not args.no_profile, budget_for(args.workload, args.precision))
     plan = res["plan"]
     entries = plan.modal_entries
     value = entries / (res["ms_per_step"] * 1e-3)
@@ -265,7 +286,9 @@ def main():
 
     fp64 = None
     if args.precision != "fp64" and not args.no_fp64:
-        r64 = time_path(sysm, s, "fp64", args.steps, args.warmup, device, False, budget)
+        torch.cuda.empty_cache()
+        r64 = time_path(sysm, s, "fp64", args.steps, args.warmup, device, False,
+                        budget_for(args.workload, "fp64"))
         v64 = entries / (r64["ms_per_step"] * 1e-3)
         e64 = errors(r64)
         fp64 = {"value": v64, "ms_per_step": r64["ms_per_step"], "rel_err": e64,

@@ -63,6 +63,9 @@ extern "C" {
 #define NPF_SRC_SPARSE 1    /* compressed by sorted tuple: for c in [0, ncols):
                                rank col_rank[c], entries col_ptr[c]..col_ptr[c+1]-1
                                with state row_k[e] and value values[e]            */
+#define NPF_SRC_HASH 2      /* generated on the device, never stored: entry (k, r) is
+                               hash_value(seed, scale, M, k, r) as defined at
+                               npf_hash_fill; needs n <= 512 and U_M < 2^40          */
 
 typedef struct npf_tensor {
     int32_t kind;
@@ -73,6 +76,8 @@ typedef struct npf_tensor {
     const int32_t *row_k;      /* sparse: [nnz], 0 <= row_k < n                       */
     int64_t ncols;
     int64_t nnz;
+    uint64_t seed;             /* hash: generator seed                               */
+    double scale;              /* hash: scale of every entry                          */
 } npf_tensor;
 
 /* Problem description (host memory; copied by npf_plan_create). */
@@ -133,6 +138,21 @@ int npf_normal_form(npf_plan_t plan, int32_t order, int64_t block, const void *l
  * prod_i delta Psi[t_i,k], with m(t) the number of orderings of t; FP64. */
 int npf_assemble(npf_plan_t plan, int32_t order, int64_t block, const void *h,
                  const void *U, void *P_acc, void *stream);
+
+/* Materialises rows [k0, k1) of a hash-generated derivative tensor (the NPF_SRC_HASH
+ * source; the paper's own tensors come from finite differences of the model, for which
+ * this generator is the synthetic stand-in): out[(k - k0)*U_M + r] (device, FP64, caller
+ * owned) for every colex rank r, U_M = binom(n + order - 1, order).  The entry is
+ *   w = SplitMix64 output number (order << 49 | k << 40 | r) from seed (Steele, Lea and
+ *       Flood 2014: z = seed + (idx + 1) * 0x9E3779B97F4A7C15, then the finaliser with
+ *       shifts 30, 27, 31 and multipliers 0xBF58476D1CE4E5B9, 0x94D049BB133111EB),
+ *   S = sum of the four 16-bit fields of w,
+ *   value = ((S - 131070) * 2^-16 * sqrt(3)) * scale, rounded in that order,
+ * an Irwin-Hall variate of mean 0 and variance scale^2.  Asynchronous on `stream`.
+ * Errors: NPF_E_INVALID for n < 1 or n > 512, order outside [2, NPF_MAX_ORDER],
+ * k0 < 0, k1 > n, k0 > k1, U_M >= 2^40 or a null out with k1 > k0. */
+int npf_hash_fill(int64_t n, int32_t order, uint64_t seed, double scale, int64_t k0,
+                  int64_t k1, double *out, void *stream);
 
 /* Alg. 2 step 20: NPF[k*n + i] = Phi[k,i] (delta Psi[i,k] + P_sum[i*n + k]).
  * P_sum may be NULL (the linear participation factors). */

@@ -7,7 +7,9 @@ no code with the HIP library; the two meet only in the seeded inputs of
 
 Functions follow the paper (arXiv 2509.08968):
   full()      Alg. 2 literally, on full tensors (small n only);
-  sym()       the same quantities from packed symmetric storage, per output mode;
+  sym()       the same quantities from packed symmetric storage, per output mode (A_M
+              stored, or generated entry by entry for hash-generated tensors);
+  hash_values()  entries of a hash-generated tensor, from the C generator;
   assemble()  Alg. 2 step 20 / eq. (7): NPF[k, i] = Phi[k, i] (delta Psi[i, k] + sum_M P_M[i, k]);
   npf()       orders 2..N of one system, summed and assembled.
 """
@@ -51,10 +53,14 @@ def lib():
             i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
             L.npfo_full.argtypes = [i64, i32, P, P, P, P, dbl, dbl, P, P, P]
             L.npfo_sym.argtypes = [i64, i32, P, P, P, P, dbl, dbl, P, i64, P, P, P, i32]
+            L.npfo_sym_hash.argtypes = [i64, i32, P, P, P, ctypes.c_uint64, dbl, dbl, dbl, P,
+                                        i64, P, P, P, i32]
+            L.npfo_hash_value.argtypes = [ctypes.c_uint64, dbl, i32, i64, i64]
+            L.npfo_hash_value.restype = dbl
             L.npfo_assemble.argtypes = [i64, P, P, dbl, P, P]
             L.npfo_binom.argtypes = [i64, i64]
             L.npfo_binom.restype = i64
-            for f in (L.npfo_full, L.npfo_sym, L.npfo_assemble):
+            for f in (L.npfo_full, L.npfo_sym, L.npfo_sym_hash, L.npfo_assemble):
                 f.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -132,15 +138,23 @@ def sym(sys, M: int, modes=None, want_C: bool = False, want_h: bool = False,
     """Packed-symmetric evaluation.  Returns dict with P [len(modes), n] and optionally
     C, h [len(modes), binom(n+M-1, M)] over colex-ranked sorted tuples."""
     n = sys.n
-    A = np.ascontiguousarray(sys.A[M] if A_packed is None else A_packed, dtype=np.float64)
+    hashed = A_packed is None and sys.A.get(M) is None and M in sys.hashed
+    A = None if hashed else np.ascontiguousarray(sys.A[M] if A_packed is None else A_packed,
+                                                 dtype=np.float64)
     modes = np.arange(n, dtype=np.int64) if modes is None else np.asarray(modes, np.int64)
     U_M = _binom(n + M - 1, M)
     C = np.empty((len(modes), U_M), np.complex128) if want_C else None
     h = np.empty((len(modes), U_M), np.complex128) if want_h else None
     P = np.empty((len(modes), n), np.complex128)
     lam, V, U = _c128(sys.lam), _c128(sys.V), _c128(sys.U)
-    rc = lib().npfo_sym(n, M, _p(lam), _p(V), _p(U), _p(A), sys.eps, sys.delta,
-                        _p(modes), len(modes), _p(C), _p(h), _p(P), int(nthreads))
+    if hashed:
+        seed, scale = sys.hashed[M]
+        rc = lib().npfo_sym_hash(n, M, _p(lam), _p(V), _p(U), int(seed), float(scale), sys.eps,
+                                 sys.delta, _p(modes), len(modes), _p(C), _p(h), _p(P),
+                                 int(nthreads))
+    else:
+        rc = lib().npfo_sym(n, M, _p(lam), _p(V), _p(U), _p(A), sys.eps, sys.delta,
+                            _p(modes), len(modes), _p(C), _p(h), _p(P), int(nthreads))
     if rc != 0:
         raise ValueError("npfo_sym rejected its arguments")
     out = {"P": P, "modes": modes}
@@ -149,6 +163,15 @@ def sym(sys, M: int, modes=None, want_C: bool = False, want_h: bool = False,
     if want_h:
         out["h"] = h
     return out
+
+
+def hash_values(seed: int, scale: float, M: int, k, r) -> np.ndarray:
+    """Entries A_M[k, r] of a hash-generated tensor from the C generator (one call each)."""
+    L = lib()
+    k = np.broadcast_to(np.asarray(k, np.int64), np.broadcast(k, r).shape).ravel()
+    r = np.broadcast_to(np.asarray(r, np.int64), k.shape).ravel()
+    return np.array([L.npfo_hash_value(int(seed), float(scale), int(M), int(a), int(b))
+                     for a, b in zip(k, r)])
 
 
 def assemble(sys, Psum=None):

@@ -201,13 +201,60 @@ static int64_t rank_insert(int32_t a, const int32_t *s, int m)
     return npfo_rank(merged, m + 1);
 }
 
+/* Hash-generated tensor entry (order M, state k, colex rank r): SplitMix64 output number
+ * (M << 49 | k << 40 | r) for the seed, its four 16-bit fields summed to S, and
+ * ((S - 131070) * 2^-16 * sqrt(3)) * scale, the two roundings in that order. */
+static uint64_t splitmix64_at(uint64_t seed, uint64_t idx)
+{
+    uint64_t z = seed + (idx + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double npfo_hash_value(uint64_t seed, double scale, int M, int64_t k, int64_t r)
+{
+    const uint64_t idx = ((uint64_t)M << 49) | ((uint64_t)k << 40) | (uint64_t)r;
+    const uint64_t w = splitmix64_at(seed, idx);
+    int64_t S = 0;
+    for (int q = 0; q < 4; ++q) S += (int64_t)((w >> (16 * q)) & 0xFFFFu);
+    const double x = (double)(S - 131070) * (1.0 / 65536.0);
+    const double y = x * 1.7320508075688772;
+    return y * scale;
+}
+
+static int sym_impl(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                    const double *A_packed, int hashed, uint64_t seed, double scale,
+                    double eps, double delta, const int64_t *modes, int64_t n_modes,
+                    npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads);
+
 int npfo_sym(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
              const double *A_packed, double eps, double delta,
              const int64_t *modes, int64_t n_modes,
              npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads)
 {
-    if (n < 1 || M < 2 || M > 8 || !lam || !Phi || !Psi || !A_packed || !modes || n_modes < 0 ||
-        !(eps > 0.0))
+    if (!A_packed) return -1;
+    return sym_impl(n, M, lam, Phi, Psi, A_packed, 0, 0, 0.0, eps, delta, modes, n_modes, C_sym,
+                    h_sym, P_rows, nthreads);
+}
+
+int npfo_sym_hash(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                  uint64_t seed, double scale, double eps, double delta,
+                  const int64_t *modes, int64_t n_modes,
+                  npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads)
+{
+    if (n > 512) return -1;
+    return sym_impl(n, M, lam, Phi, Psi, NULL, 1, seed, scale, eps, delta, modes, n_modes, C_sym,
+                    h_sym, P_rows, nthreads);
+}
+
+static int sym_impl(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                    const double *A_packed, int hashed, uint64_t seed, double scale,
+                    double eps, double delta, const int64_t *modes, int64_t n_modes,
+                    npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads)
+{
+    if (n < 1 || M < 2 || M > 8 || !lam || !Phi || !Psi || (!A_packed && !hashed) || !modes ||
+        n_modes < 0 || !(eps > 0.0))
         return -1;
     for (int64_t q = 0; q < n_modes; ++q)
         if (modes[q] < 0 || modes[q] >= n) return -1;
@@ -236,7 +283,10 @@ int npfo_sym(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_
 #pragma omp parallel for schedule(static)
         for (int64_t r = 0; r < UM; ++r) {
             npfo_c s = 0;
-            for (int64_t k = 0; k < n; ++k) s = s + Psi[j * n + k] * A_packed[k * UM + r];
+            for (int64_t k = 0; k < n; ++k) {
+                const double a = hashed ? npfo_hash_value(seed, scale, M, k, r) : A_packed[k * UM + r];
+                s = s + Psi[j * n + k] * a;
+            }
             Tprev[r] = s;
         }
         /* Lower indices one by one (Alg. 2 steps 2-3).  Stage i maps

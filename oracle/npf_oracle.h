@@ -60,6 +60,18 @@ int npfo_sym(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_
              const int64_t *modes, int64_t n_modes,
              npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads);
 
+/* Entry A_M[k, r] of a hash-generated tensor (seed, scale): SplitMix64 (Steele, Lea and
+ * Flood 2014) output number (M << 49 | k << 40 | r) from the seed; S = sum of its four
+ * 16-bit fields; value = ((S - 131070) * 2^-16 * sqrt(3)) * scale (Irwin-Hall sum of
+ * four uniforms, mean 0, variance about scale^2). */
+double npfo_hash_value(uint64_t seed, double scale, int M, int64_t k, int64_t r);
+
+/* npfo_sym with A_M generated entry by entry by npfo_hash_value (n <= 512). */
+int npfo_sym_hash(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                  uint64_t seed, double scale, double eps, double delta,
+                  const int64_t *modes, int64_t n_modes,
+                  npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads);
+
 /* NPF[k*n+i] = Phi[k,i] * (delta Psi[i,k] + Psum[i*n+k]); Psum may be NULL (linear PF). */
 int npfo_assemble(int64_t n, const npfo_c *Phi, const npfo_c *Psi, double delta,
                   const npfo_c *Psum, npfo_c *npf);

@@ -20,12 +20,13 @@ NPF_OK, NPF_E_INVALID, NPF_E_BUDGET, NPF_E_DEVICE, NPF_E_UNSUPPORTED = 0, 1, 2, 
 NPF_MAX_ORDER = 6
 NPF_ALL_BLOCKS = -1
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-SRC_DENSE, SRC_SPARSE = 0, 1
+SRC_DENSE, SRC_SPARSE, SRC_HASH = 0, 1, 2
 
 EXPORTED = [
     "npf_plan_create", "npf_plan_info", "npf_plan_destroy", "npf_modal_contract",
     "npf_normal_form", "npf_assemble", "npf_finalize", "npf_run", "npf_alg1_batches",
     "npf_plan_profile", "npf_plan_kernel_times", "npf_error_string", "npf_last_error",
+    "npf_hash_fill",
 ]
 
 
@@ -41,6 +42,7 @@ class NpfTensor(ctypes.Structure):
         ("values", ctypes.c_void_p), ("col_rank", ctypes.c_void_p),
         ("col_ptr", ctypes.c_void_p), ("row_k", ctypes.c_void_p),
         ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("seed", ctypes.c_uint64), ("scale", ctypes.c_double),
     ]
 
 
@@ -99,13 +101,14 @@ def lib():
         L.npf_plan_profile.argtypes = [P, i32]
         L.npf_plan_kernel_times.argtypes = [P, ctypes.POINTER(NpfKernelTime), i32,
                                             ctypes.POINTER(i32)]
+        L.npf_hash_fill.argtypes = [i64, i32, ctypes.c_uint64, dbl, i64, i64, P, P]
         L.npf_error_string.argtypes = [ctypes.c_int]
         L.npf_error_string.restype = ctypes.c_char_p
         L.npf_last_error.argtypes = []
         L.npf_last_error.restype = ctypes.c_char_p
         for f in ("npf_plan_create", "npf_plan_info", "npf_modal_contract", "npf_normal_form",
                   "npf_assemble", "npf_finalize", "npf_run", "npf_plan_profile",
-                  "npf_plan_kernel_times"):
+                  "npf_plan_kernel_times", "npf_hash_fill"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -261,6 +264,19 @@ def upload_tensor(A: np.ndarray, order: int, device, sparse: bool = False,
     return DeviceTensor(order, SRC_SPARSE, t, desc)
 
 
+def hash_tensor(order: int, seed: int, scale: float) -> DeviceTensor:
+    """Descriptor of a hash-generated tensor (generated on the device, nothing stored)."""
+    desc = NpfTensor(SRC_HASH, order, None, None, None, None, 0, 0, int(seed), float(scale))
+    return DeviceTensor(order, SRC_HASH, {}, desc)
+
+
+def hash_fill(n: int, order: int, seed: int, scale: float, k0: int, k1: int, out, stream=None):
+    """npf_hash_fill: rows [k0, k1) of a hash-generated tensor into the float64 device
+    tensor ``out`` (at least (k1 - k0) * binom(n + order - 1, order) elements)."""
+    _check(lib().npf_hash_fill(n, order, int(seed), float(scale), k0, k1, _ptr(out),
+                               _stream(stream)), "npf_hash_fill")
+
+
 @dataclass
 class DeviceSystem:
     n: int
@@ -271,8 +287,11 @@ class DeviceSystem:
     orders: List[int]
 
 
-def upload_system(sys, device, sparse: Optional[bool] = None) -> DeviceSystem:
-    """Copy one operating point (inputs.System) to the device."""
+def upload_system(sys, device, sparse: Optional[bool] = None,
+                  hash_source: bool = True) -> DeviceSystem:
+    """Copy one operating point (inputs.System) to the device.  Hash-generated orders get
+    a generator descriptor (nothing is copied) unless ``hash_source`` is False and the
+    system holds the materialised tensor."""
     import torch
 
     def c128(a):
@@ -281,6 +300,9 @@ def upload_system(sys, device, sparse: Optional[bool] = None) -> DeviceSystem:
     tens = []
     for M in range(2, sys.order_max + 1):
         A = sys.A.get(M)
+        if M in sys.hashed and (A is None or hash_source):
+            tens.append(hash_tensor(M, *sys.hashed[M]))
+            continue
         if A is None:
             A = np.zeros((sys.n, 1))
             tens.append(upload_tensor(A, M, device, sparse=True, support=np.zeros(0, np.int64)))
@@ -292,10 +314,11 @@ def upload_system(sys, device, sparse: Optional[bool] = None) -> DeviceSystem:
 
 
 def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0,
-            block_modes: int = 0, sparse: Optional[bool] = None, graph: bool = True):
+            block_modes: int = 0, sparse: Optional[bool] = None, graph: bool = True,
+            hash_source: bool = True):
     """Run the fused hot path on one system; returns (NPF, {M: P_M}) as numpy arrays."""
     import torch
-    dev = upload_system(sys, device, sparse)
+    dev = upload_system(sys, device, sparse, hash_source)
     plan = Plan(sys.n, sys.order_max, precision, sys.eps, sys.tau, sys.delta, budget_bytes,
                 block_modes, graph)
     ws = plan.workspace(device)

@@ -32,7 +32,7 @@ def launch_names(workload: str, precision: str, budget: int = 0):
     plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget)
     names = ["prepare"]
     for M in range(2, s.order_max + 1):
-        sparse = s.support.get(M) is not None
+        sparse = s.support.get(M) is not None and M not in s.hashed
         for _ in range(plan.n_blocks):
             if sparse:
                 names += [f"o{M}_psi_a.clear", f"o{M}_psi_a"]
@@ -83,10 +83,10 @@ def traffic(workload, precision, fetch_csv, write_csv, copy_mib, budget=0):
 
 def main(argv):
     workload, precision, fetch_csv, write_csv, copy_mib, stats_csv, out_dir, cmd = argv[:8]
-    budget = {"n128-o4-dense-resonant": 64 << 30}.get(workload, 0)
-    t = traffic(workload, precision, fetch_csv, write_csv, float(copy_mib), budget)
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
+    budget = bench.budget_for(workload, precision)
+    t = traffic(workload, precision, fetch_csv, write_csv, float(copy_mib), budget)
     js = {"workload": workload, "precision": precision,
           "source_digest": bench.kernel_source_digest(), "kernels": t,
           "note": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled "

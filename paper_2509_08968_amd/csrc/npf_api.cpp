@@ -1,4 +1,5 @@
 // C ABI entry points: argument checks, block loops and kernel sequencing.
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -29,6 +30,12 @@ int check_tensor(const npf_plan_s *p, const npf_tensor *A, int M)
             return fail(NPF_E_INVALID, "sparse tensor with a null array");
         if (A->ncols < 0 || A->ncols > p->U[M] || A->nnz < 0)
             return fail(NPF_E_INVALID, "sparse tensor sizes out of range");
+        return NPF_OK;
+    }
+    if (A->kind == NPF_SRC_HASH) {
+        if (p->n > 512 || p->U[M] >= (int64_t(1) << 40))
+            return fail(NPF_E_UNSUPPORTED, "hash-generated tensors need n <= 512 and U_M < 2^40");
+        if (!std::isfinite(A->scale)) return fail(NPF_E_INVALID, "hash tensor scale is not finite");
         return NPF_OK;
     }
     return fail(NPF_E_INVALID, "unknown tensor kind");
@@ -171,6 +178,21 @@ extern "C" int npf_finalize(npf_plan_t plan, const void *U, const void *V, const
                                      static_cast<double *>(npf_out),
                                      static_cast<hipStream_t>(stream)),
                      "finalize");
+}
+
+extern "C" int npf_hash_fill(int64_t n, int32_t order, uint64_t seed, double scale, int64_t k0,
+                             int64_t k1, double *out, void *stream)
+{
+    if (n < 1 || n > 512) return fail(NPF_E_INVALID, "hash tensors need 1 <= n <= 512");
+    if (order < 2 || order > NPF_MAX_ORDER) return fail(NPF_E_INVALID, "order outside [2, 6]");
+    if (k0 < 0 || k1 > n || k0 > k1) return fail(NPF_E_INVALID, "row range outside [0, n]");
+    const int64_t UM = binom(n + order - 1, order);
+    if (UM >= (int64_t(1) << 40)) return fail(NPF_E_INVALID, "U_M >= 2^40");
+    if (k1 == k0) return NPF_OK;
+    if (!out) return fail(NPF_E_INVALID, "null output");
+    return check_hip(launch_hash_fill(out, seed, scale, order, k0, k1 - k0, UM,
+                                      static_cast<hipStream_t>(stream)),
+                     "hash_fill");
 }
 
 namespace {

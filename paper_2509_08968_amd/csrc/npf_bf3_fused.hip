@@ -1,0 +1,235 @@
+// Split-BF16 fused last stage for systems of up to 64 states.
+#include "npf_bf3.h"
+
+namespace npf {
+
+namespace {
+
+// ------------------------------------------------------------------ fused last stage
+template <int NP, int M>
+__global__ void __launch_bounds__(kThreads)
+fused_bf3(Bf3Args a)
+{
+    constexpr int NKT = NP / 16, KC = NP / 32, N2 = NP * NP;
+    extern __shared__ __align__(16) char lds[];
+    __bf16 *Lphi = reinterpret_cast<__bf16 *>(lds);
+    __bf16 *Lz = reinterpret_cast<__bf16 *>(lds + 12 * N2);
+    float2 *Lz32 = reinterpret_cast<float2 *>(lds + 24 * N2);
+    double2 *Llam = reinterpret_cast<double2 *>(lds + 32 * N2);
+    copy_to_lds<NP>(lds, a.phiE, 12 * N2);
+    copy_to_lds<NP>(lds + 12 * N2, a.zetaE, 12 * N2);
+    copy_to_lds<NP>(lds + 24 * N2, a.zeta32, 8 * N2);
+    for (int t = threadIdx.x; t < NP; t += blockDim.x)
+        Llam[t] = t < a.n ? a.lam[t] : make_double2(0.0, 0.0);
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
+    const bool wave_on = jw < a.Jpad;
+    const int64_t jl = jw + c;
+    const bool j_ok = wave_on && jl < a.J;
+    const double2 lam_j = j_ok ? Llam[a.j0 + jl] : make_double2(0.0, 0.0);
+    // Below this |D|^2 (FP32) the divisor is finished in FP64: the tau band, and a margin
+    // around eps so that the clamp is decided in FP64 exactly as specified.
+    const float guard = fmaxf(float(a.tau2), float(4.0 * a.eps * a.eps));
+
+    double pacc_r[NKT][4], pacc_i[NKT][4];
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pacc_r[kt][r] = pacc_i[kt][r] = 0.0;
+
+    const float2 *X = static_cast<const float2 *>(a.X);
+    float2 xn[KC][8];
+    auto load_x = [&](int64_t it) {
+        const float2 *Xp = X + it * a.n * a.Jpad + jw + c;
+        const int jp = int(a.Jpad), nn = int(a.n);
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int ar = kc * 32 + 8 * g + s;
+                xn[kc][s] = ar < nn ? Xp[ar * jp] : make_float2(0.f, 0.f);
+            }
+    };
+    int64_t it = blockIdx.x;
+    uint64_t pk_next = 0;
+    if (wave_on && it < a.items) {
+        load_x(it);
+        pk_next = a.ptab[it];
+    }
+    if (wave_on)
+    for (; it < a.items; it += gridDim.x) {
+        // Split this item's rows, then start loading the next item's into the same registers.
+        Split3 xr[KC], xi[KC], xn_[KC];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            split_x(xn[kc], xr[kc], xi[kc]);
+            xn_[kc] = negx3(xi[kc]);
+        }
+        const uint64_t pk = pk_next;
+        const int64_t itn = it + gridDim.x;
+        if (itn < a.items) {
+            load_x(itn);
+            pk_next = a.ptab[itn];
+        }
+        // Item constants (M is a compile-time constant: the tuple lives in registers).
+        int32_t p[M - 1];
+#pragma unroll
+        for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
+        double2 lam_p = Llam[p[0]];
+        double den = 1.0;
+        int run = 1;
+#pragma unroll
+        for (int q = 1; q < M - 1; ++q) {
+            lam_p = add_fp64(lam_p, Llam[p[q]]);
+            if (p[q] == p[q - 1]) {
+                ++run;
+                den *= double(run);
+            } else {
+                run = 1;
+            }
+        }
+        const int m = p[M - 2];
+        const double w_gt = -1.0 / den, w_eq = -1.0 / (den * double(run + 1));
+        const float w_gt_f = float(w_gt), w_eq_f = float(w_eq);
+
+        v4f rr[NKT], ri[NKT];
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) rr[kt] = ri[kt] = v4f{0, 0, 0, 0};
+
+        for (int tc = m / 32; tc < KC; ++tc) {
+            const int t0 = tc * 32;
+            v4f sr[2], si[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) sr[u] = si[u] = v4f{0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    Split3 pr, pi;
+                    phi_frags<NP>(Lphi, kc * 32, t0 + 16 * u + c, g, pr, pi);
+                    sr[u] = mm6(pr, xr[kc], sr[u]);
+                    sr[u] = mm6(pi, xn_[kc], sr[u]);
+                    si[u] = mm6(pr, xi[kc], si[u]);
+                    si[u] = mm6(pi, xr[kc], si[u]);
+                }
+            // Divisor and division (FP64 divisor) into the A operand of the reduction.
+            float hre[8], him[8];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int u = s >> 2, r = s & 3;
+                const int t = t0 + 16 * u + 4 * g + r;
+                float vr = 0.f, vi = 0.f;
+                if (j_ok && t >= m && t < a.n) {
+                    // D in FP64 in the fixed summation order; the clamp and the division
+                    // run in FP64 below the guard (|D| < tau, or near eps), else in FP32.
+                    const double2 acc = add_fp64(lam_p, Llam[t]);
+                    const double2 d = make_double2(acc.x - lam_j.x, acc.y - lam_j.y);
+                    const float dx = float(d.x), dy = float(d.y);
+                    const float dd = dx * dx + dy * dy;
+                    const float w = (t == m) ? w_eq_f : w_gt_f;
+                    const float sx = sr[u][r], sy = si[u][r];
+                    if (dd < guard) {
+                        const double2 dc = divisor_fp64(acc, lam_j, a.eps);
+                        const double f = ((t == m) ? w_eq : w_gt) / (dc.x * dc.x + dc.y * dc.y);
+                        vr = float((double(sx) * dc.x + double(sy) * dc.y) * f);
+                        vi = float((double(sy) * dc.x - double(sx) * dc.y) * f);
+                    } else {
+                        float rc = __builtin_amdgcn_rcpf(dd);
+                        rc = rc * (2.0f - dd * rc);          // one Newton step
+                        const float f = w * rc;
+                        vr = (sx * dx + sy * dy) * f;
+                        vi = (sy * dx - sx * dy) * f;
+                    }
+                }
+                hre[s] = vr;
+                him[s] = vi;
+            }
+            const Split3 ar_ = split8(hre), ai_ = split8(him);
+            const Split3 an_ = negx3(ai_);
+#pragma unroll
+            for (int kt = 0; kt < NKT; ++kt) {
+                const int k = kt * 16 + c;
+                const int z0 = int(zeta_frag_index(t0 + 4 * g, k, NP));
+                auto ld = [&](int pl) { return *reinterpret_cast<const v8bf *>(Lz + pl * N2 + z0); };
+                Split3 zr_, zi_;
+                zr_.h = ld(0); zr_.m = ld(1); zr_.l = ld(2);
+                zi_.h = ld(3); zi_.m = ld(4); zi_.l = ld(5);
+                rr[kt] = mm6(ar_, zr_, rr[kt]);
+                rr[kt] = mm6(an_, zi_, rr[kt]);
+                ri[kt] = mm6(ar_, zi_, ri[kt]);
+                ri[kt] = mm6(ai_, zr_, ri[kt]);
+            }
+        }
+        // P += zp * R in FP64, zp[k] = prod_i zeta[p_i][k].
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+            const int k = kt * 16 + c;
+            float2 z = Lz32[p[0] * NP + k];
+#pragma unroll
+            for (int q = 1; q < M - 1; ++q) {
+                const float2 w = Lz32[p[q] * NP + k];
+                z = make_float2(z.x * w.x - z.y * w.y, z.x * w.y + z.y * w.x);
+            }
+            // The item's product zp * R is formed in FP32 (one rounding); the sum over
+            // items is kept in FP64.
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float vr = rr[kt][r], vi = ri[kt][r];
+                pacc_r[kt][r] += double(vr * z.x - vi * z.y);
+                pacc_i[kt][r] += double(vr * z.y + vi * z.x);
+            }
+        }
+    }
+    if (!wave_on) return;
+    double2 *dst = a.parts + int64_t(blockIdx.x) * a.Jpad * a.n;
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) {
+        const int64_t k = kt * 16 + c;
+        if (k >= a.n) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t j = jw + 4 * g + r;
+            dst[j * a.n + k] = make_double2(pacc_r[kt][r], pacc_i[kt][r]);
+        }
+    }
+}
+
+}  // namespace
+
+bool bf3_small_supported(const npf_plan_s *p)
+{
+    return p->prec == NPF_BF16X3 && (p->npad == 32 || p->npad == 64) && p->N <= 4;
+}
+
+hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
+                            char *ws, int64_t groups, hipStream_t s)
+{
+    Bf3Args a = base_args(p, ws, lam);
+    a.X = ws + p->lay.buf[(M - 1) % 2];
+    a.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
+    a.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
+    a.J = J;
+    a.j0 = j0;
+    a.items = p->U[M - 1];
+    a.M = M;
+    const dim3 grid{unsigned(groups), unsigned((p->Jpad + 63) / 64), 1u};
+    const size_t shm = size_t(32 * p->npad * p->npad + 16 * p->npad);
+#define NPF_FUSED_CASE(NP_, M_)                                                   \
+    if (p->npad == NP_ && M == M_) {                                             \
+        set_lds_limit(fused_bf3<NP_, M_>, int(shm));                              \
+        hipLaunchKernelGGL((fused_bf3<NP_, M_>), grid, dim3(kThreads), shm, s, a); \
+        return hipGetLastError();                                                 \
+    }
+    NPF_FUSED_CASE(32, 2) NPF_FUSED_CASE(32, 3) NPF_FUSED_CASE(32, 4)
+    NPF_FUSED_CASE(64, 2) NPF_FUSED_CASE(64, 3) NPF_FUSED_CASE(64, 4)
+#undef NPF_FUSED_CASE
+    return hipErrorInvalidValue;
+}
+
+// Items taken at once by a workgroup of the t-range kernels: four waves of 16 modes share
+// the block's 16-mode tiles, the remaining waves take further items.
+
+}  // namespace npf

@@ -1,0 +1,291 @@
+// Split-BF16 fused last stage for systems of 65 to 256 states.
+#include "npf_bf3.h"
+
+namespace npf {
+
+namespace {
+
+// ------------------------------------------------------------------ fused last stage, n > 64
+// Same arithmetic as fused_bf3; a workgroup owns one 32-wide t-slice (grid.z) of every
+// item: the slices of Phi^T and zeta live in LDS, the reduction runs over the slice's t
+// only, and the partial P of each (item group, slice, item slot) is summed with the others
+// in the fixed-order partial sums (P is linear in the sum over t).
+//
+// Waves and modes: a wave owns 16 output modes.  With fewer than four 16-mode tiles in the
+// block, the four waves take IPW = 4 / tiles items at once (item slot = wave / (4 / IPW)),
+// each slot writing its own partial.  For NP > 128 the states k of the reduction are split
+// in KS ranges over grid.y (the first product is recomputed per range) so that the FP64
+// accumulators and the zeta slice fit.
+template <int NP, int M, int IPW, int KS>
+__global__ void __launch_bounds__(kThreads)
+fused_bf3_tr(Bf3Args a)
+{
+    constexpr int NKT = NP / 16 / KS, KC = NP / 32, AG = NP / 8, N2 = NP * NP;
+    constexpr int KW = NKT * 16;     // states k of this workgroup's range
+    constexpr int WPI = 4 / IPW;     // waves per item
+    constexpr int PLP = NP * 32;     // elements per LDS plane of the Phi^T slice
+    constexpr int PLZ = 32 * KW;     // elements per LDS plane of the zeta slice
+    extern __shared__ __align__(16) char lds[];
+    __bf16 *Lphi = reinterpret_cast<__bf16 *>(lds);
+    __bf16 *Lz = reinterpret_cast<__bf16 *>(lds + 12 * PLP);
+    double2 *Llam = reinterpret_cast<double2 *>(lds + 12 * PLP + 12 * PLZ);
+    const int slice = int(blockIdx.z), t_base = slice * 32;
+    const int kh = int(blockIdx.y) % KS, jgrp = int(blockIdx.y) / KS;
+    const int k_base = kh * KW;
+    {
+        const int4 *gp = reinterpret_cast<const int4 *>(a.phiE);
+        int4 *lp = reinterpret_cast<int4 *>(Lphi);
+        for (int x = threadIdx.x; x < 6 * AG * 32; x += blockDim.x) {
+            const int tl = x % 32, ag = (x / 32) % AG, pl = x / (32 * AG);
+            lp[x] = gp[(int64_t(pl) * AG + ag) * NP + t_base + tl];
+        }
+        // zeta planes are in fragment order [pl][t/32][g][k][s]: copy this slice's rows for
+        // the workgroup's k range as [pl][g][k - k_base][s].
+        const int4 *gz = reinterpret_cast<const int4 *>(a.zetaE);
+        int4 *lz = reinterpret_cast<int4 *>(Lz);
+        for (int x = threadIdx.x; x < 6 * 4 * KW; x += blockDim.x) {
+            const int kk = x % KW, gg = (x / KW) % 4, pl = x / (4 * KW);
+            lz[x] = gz[int64_t(pl) * (N2 / 8) + (int64_t(slice) * 4 + gg) * NP + k_base + kk];
+        }
+        for (int t = threadIdx.x; t < NP; t += blockDim.x)
+            Llam[t] = t < a.n ? a.lam[t] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int islot = wave / WPI;
+    const int64_t jw = (int64_t(jgrp) * WPI + wave % WPI) * 16;
+    const bool wave_on = jw < a.Jpad && islot < IPW;
+    const int64_t jl = jw + c;
+    const bool j_ok = wave_on && jl < a.J;
+    const double2 lam_j = j_ok ? Llam[a.j0 + jl] : make_double2(0.0, 0.0);
+    const float guard = fmaxf(float(a.tau2), float(4.0 * a.eps * a.eps));
+    const int nn = int(a.n), jp = int(a.Jpad);
+    const int64_t istride = int64_t(gridDim.x) * IPW;
+
+    double pacc_r[NKT][4], pacc_i[NKT][4];
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pacc_r[kt][r] = pacc_i[kt][r] = 0.0;
+
+    const float2 *X = static_cast<const float2 *>(a.X);
+    auto load_chunk = [&](int64_t it, int kc, float2 (&dst)[8]) {
+        const float2 *Xp = X + it * a.n * a.Jpad + jw + c;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int ar = kc * 32 + 8 * g + s;
+            dst[s] = ar < nn ? Xp[ar * jp] : make_float2(0.f, 0.f);
+        }
+    };
+    auto last_of = [&](uint64_t pk) { return int((pk >> (8 * (M - 2))) & 0xff); };
+    // The slice has work for an item when some t in it is >= last(p).
+    auto active = [&](uint64_t pk) { return t_base + 32 > last_of(pk); };
+
+    int64_t it = int64_t(blockIdx.x) * IPW + islot;
+    uint64_t pk = (it < a.items) ? a.ptab[it] : 0;
+    float2 cur[8];
+    if (wave_on && it < a.items && active(pk)) load_chunk(it, 0, cur);
+    if (wave_on)
+    for (; it < a.items; it += istride) {
+        const int64_t itn = it + istride;
+        const uint64_t pkn = (itn < a.items) ? a.ptab[itn] : 0;
+        const bool next_on = itn < a.items && active(pkn);
+        if (!active(pk)) {
+            if (next_on) load_chunk(itn, 0, cur);
+            pk = pkn;
+            continue;
+        }
+        int32_t p[M - 1];
+#pragma unroll
+        for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
+        double2 lam_p = Llam[p[0]];
+        double den = 1.0;
+        int run = 1;
+#pragma unroll
+        for (int q = 1; q < M - 1; ++q) {
+            lam_p = add_fp64(lam_p, Llam[p[q]]);
+            if (p[q] == p[q - 1]) {
+                ++run;
+                den *= double(run);
+            } else {
+                run = 1;
+            }
+        }
+        const int m = p[M - 2];
+        const double w_gt = -1.0 / den, w_eq = -1.0 / (den * double(run + 1));
+        const float w_gt_f = float(w_gt), w_eq_f = float(w_eq);
+        // zp[k] = prod_i zeta[p_i][k] (FP32), loaded now and used after the products.
+        float2 zp[NKT];
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+            const int k = k_base + kt * 16 + c;
+            float2 z = a.zeta32[p[0] * NP + k];
+#pragma unroll
+            for (int q = 1; q < M - 1; ++q) {
+                const float2 w = a.zeta32[p[q] * NP + k];
+                z = make_float2(z.x * w.x - z.y * w.y, z.x * w.y + z.y * w.x);
+            }
+            zp[kt] = z;
+        }
+
+        // GEMM1 over the slice's two t-tiles, rows loaded one K-chunk ahead.
+        v4f sr[2], si[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) sr[u] = si[u] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            float2 nxt[8];
+            if (kc + 1 < KC) load_chunk(it, kc + 1, nxt);
+            else if (next_on) load_chunk(itn, 0, nxt);
+            Split3 xr, xi;
+            split_x(cur, xr, xi);
+            const Split3 xng = negx3(xi);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int pidx = ((kc * 4 + g) * 32 + 16 * u + c) * 8;
+                Split3 pr, pi;
+                pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PLP + pidx);
+                pr.m = *reinterpret_cast<const v8bf *>(Lphi + 1 * PLP + pidx);
+                pr.l = *reinterpret_cast<const v8bf *>(Lphi + 2 * PLP + pidx);
+                pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PLP + pidx);
+                pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PLP + pidx);
+                pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PLP + pidx);
+                sr[u] = mm6(pr, xr, sr[u]);
+                sr[u] = mm6(pi, xng, sr[u]);
+                si[u] = mm6(pr, xi, si[u]);
+                si[u] = mm6(pi, xr, si[u]);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+        }
+        // Divisor (FP64) and division into the reduction's A operand.
+        float hre[8], him[8];
+#pragma unroll
+        for (int s8 = 0; s8 < 8; ++s8) {
+            const int u = s8 >> 2, r = s8 & 3;
+            const int t = t_base + 16 * u + 4 * g + r;
+            float vr = 0.f, vi = 0.f;
+            if (j_ok && t >= m && t < nn) {
+                const double2 acc = add_fp64(lam_p, Llam[t]);
+                const double2 d = make_double2(acc.x - lam_j.x, acc.y - lam_j.y);
+                const float dx = float(d.x), dy = float(d.y);
+                const float dd = dx * dx + dy * dy;
+                const float w = (t == m) ? w_eq_f : w_gt_f;
+                const float sx = sr[u][r], sy = si[u][r];
+                if (dd < guard) {
+                    const double2 dc = divisor_fp64(acc, lam_j, a.eps);
+                    const double f = ((t == m) ? w_eq : w_gt) / (dc.x * dc.x + dc.y * dc.y);
+                    vr = float((double(sx) * dc.x + double(sy) * dc.y) * f);
+                    vi = float((double(sy) * dc.x - double(sx) * dc.y) * f);
+                } else {
+                    float rc = __builtin_amdgcn_rcpf(dd);
+                    rc = rc * (2.0f - dd * rc);
+                    const float f = w * rc;
+                    vr = (sx * dx + sy * dy) * f;
+                    vi = (sy * dx - sx * dy) * f;
+                }
+            }
+            hre[s8] = vr;
+            him[s8] = vi;
+        }
+        const Split3 ar_ = split8(hre), ai_ = split8(him);
+        const Split3 an_ = negx3(ai_);
+        // GEMM2 over the slice (K = 32 t) for every k tile, then P += zp * R in FP64.
+#pragma unroll
+        for (int kt = 0; kt < NKT; ++kt) {
+            const int z0 = (g * KW + kt * 16 + c) * 8;
+            Split3 zr_, zi_;
+            zr_.h = *reinterpret_cast<const v8bf *>(Lz + 0 * PLZ + z0);
+            zr_.m = *reinterpret_cast<const v8bf *>(Lz + 1 * PLZ + z0);
+            zr_.l = *reinterpret_cast<const v8bf *>(Lz + 2 * PLZ + z0);
+            zi_.h = *reinterpret_cast<const v8bf *>(Lz + 3 * PLZ + z0);
+            zi_.m = *reinterpret_cast<const v8bf *>(Lz + 4 * PLZ + z0);
+            zi_.l = *reinterpret_cast<const v8bf *>(Lz + 5 * PLZ + z0);
+            v4f rr = v4f{0, 0, 0, 0}, ri = v4f{0, 0, 0, 0};
+            rr = mm6(ar_, zr_, rr);
+            rr = mm6(an_, zi_, rr);
+            ri = mm6(ar_, zi_, ri);
+            ri = mm6(ai_, zr_, ri);
+            const float2 z = zp[kt];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float vr = rr[r], vi = ri[r];
+                pacc_r[kt][r] += double(vr * z.x - vi * z.y);
+                pacc_i[kt][r] += double(vr * z.y + vi * z.x);
+            }
+        }
+        pk = pkn;
+    }
+    if (!wave_on) return;
+    double2 *dst = a.parts + ((int64_t(blockIdx.z) * gridDim.x + blockIdx.x) * IPW + islot) *
+                                 a.Jpad * a.n;
+#pragma unroll
+    for (int kt = 0; kt < NKT; ++kt) {
+        const int64_t k = k_base + kt * 16 + c;
+        if (k >= a.n) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t j = jw + 4 * g + r;
+            dst[j * a.n + k] = make_double2(pacc_r[kt][r], pacc_i[kt][r]);
+        }
+    }
+}
+
+}  // namespace
+
+int bf3_items_per_group(int64_t Jpad)
+{
+    const int64_t tiles = Jpad / 16;
+    return tiles >= 3 ? 1 : int(4 / tiles);
+}
+
+// Partial slots written by the fused split-BF16 kernel for n > 64 per workgroup along x:
+// t-slices x item slots.
+int64_t fused_bf3_tr_slices(const npf_plan_s *p, int64_t Jpad)
+{
+    return p->npad / 32 * bf3_items_per_group(Jpad);
+}
+
+hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J,
+                               const double *lam, char *ws, int64_t groups, hipStream_t s)
+{
+    Bf3Args a = base_args(p, ws, lam);
+    a.X = ws + p->lay.buf[(M - 1) % 2];
+    a.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
+    a.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
+    a.J = J;
+    a.j0 = j0;
+    a.items = p->U[M - 1];
+    a.M = M;
+    const int NP = int(p->npad);
+    const int ipw = bf3_items_per_group(p->Jpad);
+    const int ks = NP > 128 ? 2 : 1;
+    const int64_t jgroups = (p->Jpad / 16 * ipw + 3) / 4;
+    const dim3 grid{unsigned(groups), unsigned(jgroups * ks), unsigned(NP / 32)};
+    const size_t shm = size_t(12 * NP * 32 + 12 * 32 * (NP / ks) + 16 * NP);
+#define NPF_FUSED_TR(NP_, M_, IPW_)                                                             \
+    if (NP == NP_ && M == M_ && ipw == IPW_) {                                                 \
+        constexpr int KS_ = NP_ > 128 ? 2 : 1;                                                 \
+        set_lds_limit(fused_bf3_tr<NP_, M_, IPW_, KS_>, int(shm));                              \
+        hipLaunchKernelGGL((fused_bf3_tr<NP_, M_, IPW_, KS_>), grid, dim3(kThreads), shm, s, a); \
+        return hipGetLastError();                                                               \
+    }
+#define NPF_FUSED_TR_NP(NP_)                                                           \
+    NPF_FUSED_TR(NP_, 2, 1) NPF_FUSED_TR(NP_, 3, 1) NPF_FUSED_TR(NP_, 4, 1)            \
+    NPF_FUSED_TR(NP_, 2, 2) NPF_FUSED_TR(NP_, 3, 2) NPF_FUSED_TR(NP_, 4, 2)            \
+    NPF_FUSED_TR(NP_, 2, 4) NPF_FUSED_TR(NP_, 3, 4) NPF_FUSED_TR(NP_, 4, 4)
+    NPF_FUSED_TR_NP(96) NPF_FUSED_TR_NP(128) NPF_FUSED_TR_NP(160) NPF_FUSED_TR_NP(192)
+    NPF_FUSED_TR_NP(224) NPF_FUSED_TR_NP(256)
+#undef NPF_FUSED_TR_NP
+#undef NPF_FUSED_TR
+    return hipErrorInvalidValue;
+}
+
+bool bf3_tr_fused_supported(const npf_plan_s *p)
+{
+    return p->prec == NPF_BF16X3 && p->npad >= 96 && p->npad <= 256 && p->N <= 4;
+}
+
+}  // namespace npf

@@ -1,0 +1,150 @@
+// Split-BF16 chain stage for systems of up to 64 states.
+#include "npf_bf3.h"
+
+namespace npf {
+
+namespace {
+
+// ------------------------------------------------------------------ one chain stage
+template <int NP, int SUF>
+__global__ void __launch_bounds__(kThreads)
+stage_bf3(Bf3Args a)
+{
+    constexpr int NTT = NP / 16, KC = NP / 32;
+    extern __shared__ __align__(16) char lds[];
+    __shared__ int32_t sidx[2][NP];
+    __shared__ int64_t rowoff[NP];      // binom(t + i - 1, i) * U_suf * Jpad
+    const __bf16 *Lphi = reinterpret_cast<const __bf16 *>(lds);
+    copy_to_lds<NP>(lds, a.phiE, 12 * NP * NP);
+    for (int t = threadIdx.x; t < NP; t += blockDim.x)
+        rowoff[t] = colex_term_c(t, a.i) * a.U_suf * a.Jpad;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
+    const bool wave_on = jw < a.Jpad;
+    const float2 *X = static_cast<const float2 *>(a.X);
+
+    auto build_idx = [&](int64_t it, int buf) {
+        const int64_t rs = it % a.U_suf;
+        const uint64_t pk = a.stab[rs];
+        if (threadIdx.x < a.n) {
+            // rank(sort({x} U s)) for the sorted suffix s (SUF entries, in registers).
+            const int32_t x = int32_t(threadIdx.x);
+            int64_t r = 0;
+            int qq = 0;
+#pragma unroll
+            for (int l = 0; l < SUF; ++l) {
+                const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
+                if (sl <= x) {
+                    r += colex_term_c(sl, l + 1);
+                    ++qq;
+                } else {
+                    r += colex_term_c(sl, l + 2);
+                }
+            }
+            sidx[buf][threadIdx.x] = int32_t(r + colex_term_c(x, qq + 1));
+        }
+    };
+    float2 xn[KC][8];
+    auto gather_x = [&](int64_t it, int buf) {
+        const int64_t rp = it / a.U_suf;
+        const float2 *src = X + rp * a.U_in * a.Jpad + jw + c;
+        const unsigned jp = unsigned(a.Jpad);
+        const int nn = int(a.n);
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int ar = kc * 32 + 8 * g + s;
+                xn[kc][s] = ar < nn ? src[uint64_t(unsigned(sidx[buf][ar])) * jp]
+                                    : make_float2(0.f, 0.f);
+            }
+    };
+
+    int64_t it = blockIdx.x;
+    int buf = 0;
+    if (it < a.items) build_idx(it, 0);
+    __syncthreads();          // also orders the LDS copy of Phi
+    if (it < a.items && wave_on) gather_x(it, 0);
+    for (; it < a.items; it += gridDim.x, buf ^= 1) {
+        Split3 xr[KC], xi[KC], xn_[KC];
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            split_x(xn[kc], xr[kc], xi[kc]);
+            xn_[kc] = negx3(xi[kc]);
+        }
+        const int64_t itn = it + gridDim.x;
+        if (itn < a.items) build_idx(itn, buf ^ 1);
+        __syncthreads();
+        if (itn < a.items && wave_on) gather_x(itn, buf ^ 1);
+        if (!wave_on) continue;
+
+        const int64_t rp = it / a.U_suf, rs = it % a.U_suf;
+        int m = 0;
+        if (a.i > 1) m = int((a.ptab[rp] >> (8 * (a.i - 2))) & 0xff);
+        const int tt0 = m / 16;
+
+        v4f sr[NTT], si[NTT];
+#pragma unroll
+        for (int tt = 0; tt < NTT; ++tt) sr[tt] = si[tt] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int tt = 0; tt < NTT; ++tt) {
+            if (tt < tt0) continue;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                Split3 pr, pi;
+                phi_frags<NP>(Lphi, kc * 32, tt * 16 + c, g, pr, pi);
+                sr[tt] = mm6(pr, xr[kc], sr[tt]);
+                sr[tt] = mm6(pi, xn_[kc], sr[tt]);
+                si[tt] = mm6(pr, xi[kc], si[tt]);
+                si[tt] = mm6(pi, xr[kc], si[tt]);
+            }
+        }
+        // Row rank(p U t) = rp + binom(t + i - 1, i).
+        float2 *dst = static_cast<float2 *>(a.out) + (rp * a.U_suf + rs) * a.Jpad + jw + c;
+        const int nn = int(a.n);
+#pragma unroll
+        for (int tt = 0; tt < NTT; ++tt) {
+            if (tt < tt0) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = tt * 16 + 4 * g + r;
+                if (t < m || t >= nn) continue;
+                dst[rowoff[t]] = make_float2(sr[tt][r], si[tt][r]);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_stage_bf3_small(const ChainArgs &ca, int i)
+{
+    const npf_plan_s &p = *ca.plan;
+    const Bf3Args a = stage_args(ca, i);
+    const int suf = ca.M - i;
+    const int64_t jgroups = (p.Jpad + 63) / 64;
+    int64_t groups = 512 / jgroups;
+    if (groups > a.items) groups = a.items;
+    if (groups < 1) groups = 1;
+    const dim3 grid{unsigned(groups), unsigned(jgroups), 1u};
+    const size_t shm = size_t(12 * p.npad * p.npad);
+#define NPF_STAGE_CASE(NP_, S_)                                                           \
+    if (p.npad == NP_ && suf == S_) {                                                    \
+        set_lds_limit(stage_bf3<NP_, S_>, int(shm));                                      \
+        hipLaunchKernelGGL((stage_bf3<NP_, S_>), grid, dim3(kThreads), shm, ca.stream, a); \
+        return hipGetLastError();                                                         \
+    }
+    NPF_STAGE_CASE(32, 1) NPF_STAGE_CASE(32, 2) NPF_STAGE_CASE(32, 3)
+    NPF_STAGE_CASE(64, 1) NPF_STAGE_CASE(64, 2) NPF_STAGE_CASE(64, 3)
+#undef NPF_STAGE_CASE
+    return hipErrorInvalidValue;
+}
+
+bool bf3_stage_supported(const npf_plan_s *p)
+{
+    return p->prec == NPF_BF16X3 && p->N <= 4;
+}
+
+}  // namespace npf

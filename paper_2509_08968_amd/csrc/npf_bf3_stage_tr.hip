@@ -1,0 +1,199 @@
+// Split-BF16 chain stage for systems of 65 to 256 states, and the stage dispatcher.
+#include "npf_bf3.h"
+
+namespace npf {
+
+namespace {
+
+// ------------------------------------------------------------------ one chain stage, n > 64
+// Same arithmetic as stage_bf3; a workgroup owns a range of TT t-tiles (grid.z) and keeps
+// only that slice of the Phi^T planes in LDS.  The gathered rows are loaded one K-chunk
+// ahead (the last chunk of an item prefetches the first chunk of the next item).  With
+// fewer than four 16-mode tiles in the block, the four waves take IPW items per iteration
+// (item slot = wave / (4 / IPW)).
+template <int NP, int SUF, int TT, int IPW>
+__global__ void __launch_bounds__(kThreads)
+stage_bf3_tr(Bf3Args a)
+{
+    constexpr int KC = NP / 32, TW = TT * 16, AG = NP / 8;
+    constexpr int WPI = 4 / IPW;
+    extern __shared__ __align__(16) char lds[];
+    // Gather tables, three buffers in rotation: iteration k's tables are read in iterations
+    // k-1 (the first chunk) and k (the others) and rewritten in iteration k+2 before that
+    // iteration's barrier, i.e. after every wave has passed the barrier of iteration k+1.
+    __shared__ int32_t sidx[3][IPW][NP];
+    __shared__ int64_t rowoff[TW];
+    const int t_base = int(blockIdx.z) * TW;
+    {
+        // Slice [t_base, t_base + TW) of the six planes [pl][a/8][t][a%8].
+        const int4 *gsrc = reinterpret_cast<const int4 *>(a.phiE);
+        int4 *ldst = reinterpret_cast<int4 *>(lds);
+        for (int x = threadIdx.x; x < 6 * AG * TW; x += blockDim.x) {
+            const int tl = x % TW, ag = (x / TW) % AG, pl = x / (TW * AG);
+            const int t = t_base + tl;
+            ldst[x] = (t < NP) ? gsrc[(int64_t(pl) * AG + ag) * NP + t] : int4{0, 0, 0, 0};
+        }
+        for (int tl = threadIdx.x; tl < TW; tl += blockDim.x)
+            rowoff[tl] = colex_term_c(t_base + tl, a.i) * a.U_suf * a.Jpad;
+    }
+    const __bf16 *Lphi = reinterpret_cast<const __bf16 *>(lds);
+    constexpr int PL = NP * TW;      // elements per LDS plane
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int islot = wave / WPI;
+    const int64_t jw = (int64_t(blockIdx.y) * WPI + wave % WPI) * 16;
+    const bool wave_on = jw < a.Jpad && islot < IPW;
+    const float2 *X = static_cast<const float2 *>(a.X);
+    const unsigned jp = unsigned(a.Jpad);
+    const int nn = int(a.n);
+    const int64_t istride = int64_t(gridDim.x) * IPW;
+
+    // Gather tables of the items ib .. ib + IPW - 1 into buffer buf.
+    auto build_idx = [&](int64_t ib, int buf) {
+        for (int xq = threadIdx.x; xq < IPW * nn; xq += blockDim.x) {
+            const int q = xq / nn;
+            const int64_t itq = ib + q;
+            if (itq >= a.items) break;
+            const uint64_t pk = a.stab[itq % a.U_suf];
+            const int32_t x = int32_t(xq - q * nn);
+            int64_t r = 0;
+            int qq = 0;
+#pragma unroll
+            for (int l = 0; l < SUF; ++l) {
+                const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
+                if (sl <= x) {
+                    r += colex_term_c(sl, l + 1);
+                    ++qq;
+                } else {
+                    r += colex_term_c(sl, l + 2);
+                }
+            }
+            sidx[buf][q][x] = int32_t(r + colex_term_c(x, qq + 1));
+        }
+    };
+    // last(p) of an item, and whether this workgroup's t-range has any t >= last(p).
+    auto item_m = [&](int64_t it) {
+        return (a.i > 1) ? int((a.ptab[it / a.U_suf] >> (8 * (a.i - 2))) & 0xff) : 0;
+    };
+    auto active = [&](int m) { return t_base + TW > m; };
+    auto load_chunk = [&](int64_t it, int buf, int kc, float2 (&dst)[8]) {
+        const float2 *src = X + (it / a.U_suf) * a.U_in * a.Jpad + jw + c;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int ar = kc * 32 + 8 * g + q;
+            dst[q] = ar < nn ? src[uint64_t(unsigned(sidx[buf][islot][ar])) * jp]
+                             : make_float2(0.f, 0.f);
+        }
+    };
+
+    // ib: the workgroup's first item of the iteration (uniform); it = ib + islot.
+    int64_t ib = int64_t(blockIdx.x) * IPW;
+    int buf = 0;
+    float2 cur[8];
+    if (ib < a.items) build_idx(ib, 0);
+    __syncthreads();          // also orders the LDS slice of Phi
+    if (ib + islot < a.items && wave_on && active(item_m(ib + islot))) load_chunk(ib + islot, 0, 0, cur);
+    for (; ib < a.items; ib += istride, buf = (buf == 2) ? 0 : buf + 1) {
+        const int64_t ibn = ib + istride;
+        const int nbuf = (buf == 2) ? 0 : buf + 1;
+        if (ibn < a.items) build_idx(ibn, nbuf);
+        __syncthreads();
+        const int64_t it = ib + islot, itn = ibn + islot;
+        if (!wave_on || it >= a.items) continue;
+        const int m = item_m(it);
+        const bool next_on = itn < a.items && active(item_m(itn));
+        if (!active(m)) {
+            if (next_on) load_chunk(itn, nbuf, 0, cur);
+            continue;
+        }
+        const int tt0 = (m > t_base) ? (m - t_base) / 16 : 0;
+        v4f sr[TT], si[TT];
+        // Straight-line tile loops for each first active tile (no branches between MFMAs).
+        auto sweep = [&](auto first) {
+            constexpr int T0 = decltype(first)::value;
+#pragma unroll
+            for (int tt = 0; tt < TT; ++tt) sr[tt] = si[tt] = v4f{0, 0, 0, 0};
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                float2 nxt[8];
+                if (kc + 1 < KC) load_chunk(it, buf, kc + 1, nxt);
+                else if (next_on) load_chunk(itn, nbuf, 0, nxt);
+                Split3 xr, xi;
+                split_x(cur, xr, xi);
+                const Split3 xng = negx3(xi);
+#pragma unroll
+                for (int tt = T0; tt < TT; ++tt) {
+                    const int pidx = ((kc * 4 + g) * TW + tt * 16 + c) * 8;
+                    Split3 pr, pi;
+                    pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PL + pidx);
+                    pr.m = *reinterpret_cast<const v8bf *>(Lphi + 1 * PL + pidx);
+                    pr.l = *reinterpret_cast<const v8bf *>(Lphi + 2 * PL + pidx);
+                    pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PL + pidx);
+                    pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PL + pidx);
+                    pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PL + pidx);
+                    sr[tt] = mm6(pr, xr, sr[tt]);
+                    sr[tt] = mm6(pi, xng, sr[tt]);
+                    si[tt] = mm6(pr, xi, si[tt]);
+                    si[tt] = mm6(pi, xr, si[tt]);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+            }
+        };
+        switch (tt0) {
+        case 0: sweep(std::integral_constant<int, 0>{}); break;
+        case 1: if constexpr (TT > 1) sweep(std::integral_constant<int, (TT > 1 ? 1 : 0)>{}); break;
+        case 2: if constexpr (TT > 2) sweep(std::integral_constant<int, (TT > 2 ? 2 : 0)>{}); break;
+        default: if constexpr (TT > 3) sweep(std::integral_constant<int, (TT > 3 ? 3 : 0)>{}); break;
+        }
+        const int64_t rp = it / a.U_suf, rs = it % a.U_suf;
+        float2 *dst = static_cast<float2 *>(a.out) + (rp * a.U_suf + rs) * a.Jpad + jw + c;
+#pragma unroll
+        for (int tt = 0; tt < TT; ++tt) {
+            if (tt < tt0) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int tl = tt * 16 + 4 * g + r;
+                const int t = t_base + tl;
+                if (t < m || t >= nn) continue;
+                dst[rowoff[tl]] = make_float2(sr[tt][r], si[tt][r]);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
+{
+    const npf_plan_s &p = *ca.plan;
+    if (p.npad <= 64) return launch_stage_bf3_small(ca, i);
+    const Bf3Args a = stage_args(ca, i);
+    const int suf = ca.M - i;
+    const int ipw = bf3_items_per_group(p.Jpad);
+    const int64_t jgroups = (p.Jpad / 16 * ipw + 3) / 4;
+    int64_t groups = 512 / jgroups;
+    const int64_t need = (a.items + ipw - 1) / ipw;
+    if (groups > need) groups = need;
+    if (groups < 1) groups = 1;
+#define NPF_STAGE_TR(NP_, S_, TT_, IPW_)                                                    \
+    if (p.npad == NP_ && suf == S_ && ipw == IPW_) {                                        \
+        const dim3 grid{unsigned(groups), unsigned(jgroups), unsigned((NP_ / 16 + TT_ - 1) / TT_)}; \
+        const size_t shm = size_t(12 * NP_ * TT_ * 16);                                     \
+        set_lds_limit(stage_bf3_tr<NP_, S_, TT_, IPW_>, int(shm));                           \
+        hipLaunchKernelGGL((stage_bf3_tr<NP_, S_, TT_, IPW_>), grid, dim3(kThreads), shm, ca.stream, a); \
+        return hipGetLastError();                                                            \
+    }
+#define NPF_STAGE_TR_NP(NP_, TT_)                                                     \
+    NPF_STAGE_TR(NP_, 1, TT_, 1) NPF_STAGE_TR(NP_, 2, TT_, 1) NPF_STAGE_TR(NP_, 3, TT_, 1) \
+    NPF_STAGE_TR(NP_, 1, TT_, 2) NPF_STAGE_TR(NP_, 2, TT_, 2) NPF_STAGE_TR(NP_, 3, TT_, 2) \
+    NPF_STAGE_TR(NP_, 1, TT_, 4) NPF_STAGE_TR(NP_, 2, TT_, 4) NPF_STAGE_TR(NP_, 3, TT_, 4)
+    NPF_STAGE_TR_NP(96, 3) NPF_STAGE_TR_NP(128, 4) NPF_STAGE_TR_NP(160, 2)
+    NPF_STAGE_TR_NP(192, 2) NPF_STAGE_TR_NP(224, 2) NPF_STAGE_TR_NP(256, 2)
+#undef NPF_STAGE_TR_NP
+#undef NPF_STAGE_TR
+    return hipErrorInvalidValue;
+}
+
+}  // namespace npf

@@ -32,6 +32,25 @@ __host__ __device__ __forceinline__ int64_t colex_term_c(int64_t x, int i)
     }
 }
 
+// Entry A_M[k, r] of a hash-generated derivative tensor: SplitMix64 (Steele, Lea and Flood
+// 2014) output number (M << 49 | k << 40 | r) from `seed`; the sum S of its four 16-bit
+// fields gives ((S - 131070) 2^-16 sqrt(3)) scale, an Irwin-Hall variate of mean 0 and
+// variance scale^2.  Integer work and two IEEE products: every device reproduces the bits.
+__host__ __device__ __forceinline__ double hash_entry(uint64_t seed, double scale, int M,
+                                                      int64_t k, int64_t r)
+{
+    const uint64_t idx = (uint64_t(M) << 49) | (uint64_t(k) << 40) | uint64_t(r);
+    uint64_t z = seed + (idx + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int s = int(z & 0xffffu) + int((z >> 16) & 0xffffu) + int((z >> 32) & 0xffffu) +
+                  int(z >> 48);
+    const double x = double(s - 131070) * 0x1p-16;
+    const double y = x * 1.7320508075688772;
+    return y * scale;
+}
+
 // Sorted tuples of length <= 7 over n <= 256 states are packed 8 bits per entry.
 __host__ __device__ __forceinline__ void unpack_tuple(uint64_t pk, int m, int32_t *t)
 {

@@ -477,20 +477,33 @@ hipError_t launch_fused_eng(const FusedArgs &fa, int nkt, int64_t groups, hipStr
 
 }  // namespace
 
-// Workgroups along the items of the fused kernel (grid.x).
-static int64_t fused_gx(const npf_plan_s *p, int M)
+// Workgroups along the items of the fused kernel (grid.x) for `items` items (all items
+// when items < 0) and a block of Jpad modes.
+static int64_t fused_gx(const npf_plan_s *p, int64_t items, int64_t Jpad)
 {
-    const int64_t items = p->U[M - 1];
-    const int64_t jgroups = (p->Jpad + 63) / 64;
-    int64_t g = (bf3_small_supported(p) ? 256 : (bf3_tr_fused_supported(p) ? 128 : 512)) / jgroups;
+    const bool tr = bf3_tr_fused_supported(p);
+    const int64_t ipw = tr ? bf3_items_per_group(Jpad) : 1;
+    const int64_t jgroups = (Jpad / 16 * ipw + 3) / 4;
+    int64_t g = (bf3_small_supported(p) ? 256 : (tr ? 128 : 512)) / jgroups;
     if (g < 1) g = 1;
-    return items < g ? items : g;
+    if (items >= 0) {
+        const int64_t need = (items + ipw - 1) / ipw;
+        if (need < g) g = need > 0 ? need : 1;
+    }
+    return g;
 }
 
 // Partial-P slots written by the fused kernel for order M.
 int64_t fused_groups(const npf_plan_s *p, int M)
 {
-    return fused_gx(p, M) * (bf3_tr_fused_supported(p) ? fused_bf3_tr_slices(p) : 1);
+    return fused_gx(p, p->U[M - 1], p->Jpad) *
+           (bf3_tr_fused_supported(p) ? fused_bf3_tr_slices(p, p->Jpad) : 1);
+}
+
+// Most partial-P slots any order can write for a block of Jpad modes (workspace sizing).
+int64_t fused_max_slots(const npf_plan_s *p, int64_t Jpad)
+{
+    return fused_gx(p, -1, Jpad) * (bf3_tr_fused_supported(p) ? fused_bf3_tr_slices(p, Jpad) : 1);
 }
 
 hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V, char *ws,
@@ -532,7 +545,7 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
     fa.eps = p->prob.eps;
     fa.tau2 = p->prob.tau * p->prob.tau;
     const int nkt = int(p->npad / 16);
-    const int64_t groups = fused_gx(p, M);
+    const int64_t groups = fused_gx(p, p->U[M - 1], p->Jpad);
     if (bf3_small_supported(p)) return launch_fused_bf3(p, M, j0, J, lam, ws, groups, s);
     if (bf3_tr_fused_supported(p)) return launch_fused_bf3_tr(p, M, j0, J, lam, ws, groups, s);
     switch (p->prec) {

@@ -106,6 +106,9 @@ struct ChainArgs {
 
 // G = Psi[j0:j0+J, :] A_M over sorted tuples, into buffer 0 (T_0).
 hipError_t launch_psi_a(const ChainArgs &a);
+// Rows [k0, k0 + rows) of a hash-generated tensor into out[(k - k0)*UM + r].
+hipError_t launch_hash_fill(double *out, uint64_t seed, double scale, int M, int64_t k0,
+                            int64_t rows, int64_t UM, hipStream_t s);
 // Stage i (1 <= i <= M-1) of the lower-index chain: T_{i-1} -> T_i.
 hipError_t launch_stage(const ChainArgs &a, int i);
 // Last stage, writes C (complex128, [J][U_M], scaled by 1/M!) to C_out.
@@ -131,13 +134,17 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
                                double *psum, bool first, char *ws, hipStream_t s);
 int64_t fused_groups(const npf_plan_s *p, int M);
+// Most partial-P slots any order writes for a block of Jpad modes.
+int64_t fused_max_slots(const npf_plan_s *p, int64_t Jpad);
 // Split-BF16 kernels with LDS-resident operands for npad <= 64.
 bool bf3_small_supported(const npf_plan_s *p);
 hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
                             char *ws, int64_t groups, hipStream_t s);
 hipError_t launch_stage_bf3(const ChainArgs &a, int i);
+hipError_t launch_stage_bf3_small(const ChainArgs &a, int i);
 bool bf3_tr_fused_supported(const npf_plan_s *p);
-int64_t fused_bf3_tr_slices(const npf_plan_s *p);
+int bf3_items_per_group(int64_t Jpad);
+int64_t fused_bf3_tr_slices(const npf_plan_s *p, int64_t Jpad);
 hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J,
                                const double *lam, char *ws, int64_t groups, hipStream_t s);
 bool bf3_stage_supported(const npf_plan_s *p);

@@ -29,7 +29,8 @@ template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v)
 template <typename C, typename Acc>
 __global__ void __launch_bounds__(kThreads)
 psi_a_dense(const double *__restrict__ A, const double2 *__restrict__ Psi, int64_t n, int64_t UM,
-            int64_t j0, int64_t J, int64_t Jpad, C *__restrict__ out)
+            int64_t j0, int64_t J, int64_t Jpad, C *__restrict__ out, int hashed, uint64_t seed,
+            double scale, int M)
 {
     const int64_t total = UM * Jpad;
     for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
@@ -39,7 +40,7 @@ psi_a_dense(const double *__restrict__ A, const double2 *__restrict__ Psi, int64
         if (jj < J) {
             const double2 *psi = Psi + (j0 + jj) * n;
             for (int64_t k = 0; k < n; ++k) {
-                const Acc a = Acc(A[k * UM + r]);
+                const Acc a = Acc(hashed ? hash_entry(seed, scale, M, k, r) : A[k * UM + r]);
                 const double2 w = psi[k];
                 re += a * Acc(w.x);
                 im += a * Acc(w.y);
@@ -49,6 +50,17 @@ psi_a_dense(const double *__restrict__ A, const double2 *__restrict__ Psi, int64
     }
 }
 
+
+// Rows [k0, k0 + rows) of a hash-generated tensor, materialised: out[(k - k0)*UM + r].
+__global__ void __launch_bounds__(kThreads)
+hash_fill(double *__restrict__ out, uint64_t seed, double scale, int M, int64_t k0, int64_t rows,
+          int64_t UM)
+{
+    const int64_t total = rows * UM;
+    for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
+         x += int64_t(gridDim.x) * blockDim.x)
+        out[x] = hash_entry(seed, scale, M, k0 + x / UM, x % UM);
+}
 
 // Sparse source, compressed by sorted tuple: T_0 row r is nonzero only if r is one of the
 // listed tuples.  The rows are cleared by fill_zero first; this kernel writes the listed
@@ -242,16 +254,20 @@ hipError_t launch_psi_a(const ChainArgs &a)
     const int64_t UM = p.U[a.M];
     char *dst = a.ws + p.lay.buf[0];
     const double2 *Psi = reinterpret_cast<const double2 *>(a.U);
-    if (a.A->kind == NPF_SRC_DENSE && psi_a_mfma_supported(&p)) return launch_psi_a_mfma(a);
-    if (a.A->kind == NPF_SRC_DENSE) {
+    const bool dense = a.A->kind == NPF_SRC_DENSE || a.A->kind == NPF_SRC_HASH;
+    const int hashed = a.A->kind == NPF_SRC_HASH;
+    if (dense && psi_a_mfma_supported(&p)) return launch_psi_a_mfma(a);
+    if (dense) {
         if (p.prec == NPF_FP64)
             hipLaunchKernelGGL((psi_a_dense<double2, double>), dim3(grid_for(UM * p.Jpad)),
                                dim3(kThreads), 0, a.stream, a.A->values, Psi, p.n, UM, a.j0, a.J,
-                               p.Jpad, reinterpret_cast<double2 *>(dst));
+                               p.Jpad, reinterpret_cast<double2 *>(dst), hashed, a.A->seed,
+                               a.A->scale, a.M);
         else
             hipLaunchKernelGGL((psi_a_dense<float2, float>), dim3(grid_for(UM * p.Jpad)),
                                dim3(kThreads), 0, a.stream, a.A->values, Psi, p.n, UM, a.j0, a.J,
-                               p.Jpad, reinterpret_cast<float2 *>(dst));
+                               p.Jpad, reinterpret_cast<float2 *>(dst), hashed, a.A->seed,
+                               a.A->scale, a.M);
     } else {
         const int64_t total = a.A->ncols * p.Jpad;
         if (p.prec == NPF_FP64) {
@@ -272,6 +288,15 @@ hipError_t launch_psi_a(const ChainArgs &a)
                                    p.Jpad, reinterpret_cast<float2 *>(dst));
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_fill(double *out, uint64_t seed, double scale, int M, int64_t k0,
+                            int64_t rows, int64_t UM, hipStream_t s)
+{
+    if (rows * UM > 0)
+        hipLaunchKernelGGL(hash_fill, dim3(grid_for(rows * UM)), dim3(kThreads), 0, s, out, seed,
+                           scale, M, k0, rows, UM);
     return hipGetLastError();
 }
 

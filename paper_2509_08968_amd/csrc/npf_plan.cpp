@@ -55,8 +55,7 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     L.pm = take(p.n * p.n * 16);
     L.phi_bytes = p.npad * p.npad * 16 * 4;
     L.phi = take(L.phi_bytes);
-    const int64_t jgroups = (Jpad + 63) / 64;
-    const int64_t nparts = std::max<int64_t>(1, 512 / jgroups);
+    const int64_t nparts = std::max<int64_t>(1, fused_max_slots(&p, Jpad));
     L.parts_bytes = nparts * Jpad * p.n * 16;
     L.parts = take(L.parts_bytes);
     L.parts2_bytes = ((nparts + 15) / 16) * Jpad * p.n * 16;

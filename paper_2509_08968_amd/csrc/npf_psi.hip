@@ -3,7 +3,8 @@
 // A_M is real and read once per output-mode block, so the kernel is bound by the HBM
 // stream of A_M; Psi^T for the block (n x Jpad complex) stays in LDS for the whole launch
 // and each workgroup sweeps 64-row tiles of r.  FP64 MFMA for the FP64 path, FP32 MFMA
-// (FP32 accumulation) for the FP32 and split-BF16 paths.
+// (FP32 accumulation) for the FP32 and split-BF16 paths.  For a hash-generated tensor the
+// A_M entries are generated in registers where the stored ones would be loaded.
 #include "npf_device.h"
 #include "npf_internal.h"
 #include "npf_mfma.h"
@@ -14,10 +15,18 @@ namespace {
 
 constexpr int kThreads = 256;   // 4 waves, 16 rows r each
 
-template <Eng E, int NJT>
+// Where A_M comes from: stored values, or the hash generator.
+struct ASrc {
+    const double *A;
+    uint64_t seed;
+    double scale;
+    int M;
+};
+
+template <Eng E, int NJT, bool HASH>
 __global__ void __launch_bounds__(kThreads)
-psi_a_mfma(const double *__restrict__ A, const double2 *__restrict__ Psi, int64_t n, int64_t UM,
-           int64_t j0, int64_t J, int64_t Jpad, void *__restrict__ out_)
+psi_a_mfma(ASrc src, const double2 *__restrict__ Psi, int64_t n, int64_t UM, int64_t j0,
+           int64_t J, int64_t Jpad, void *__restrict__ out_)
 {
     using T = EngT<E>;
     using acc_t = typename T::acc;
@@ -49,7 +58,11 @@ psi_a_mfma(const double *__restrict__ A, const double2 *__restrict__ Psi, int64_
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int64_t k = k0 + 4 * q + g;
-                av[q] = (r_ok && k < n) ? real(A[k * UM + r]) : real(0);
+                if constexpr (HASH)
+                    av[q] = (r_ok && k < n) ? real(hash_entry(src.seed, src.scale, src.M, k, r))
+                                            : real(0);
+                else
+                    av[q] = (r_ok && k < n) ? real(src.A[k * UM + r]) : real(0);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -73,19 +86,29 @@ psi_a_mfma(const double *__restrict__ A, const double2 *__restrict__ Psi, int64_
     }
 }
 
-template <Eng E, int NJT>
-hipError_t launch(const double *A, const double2 *Psi, int64_t n, int64_t UM, int64_t j0, int64_t J,
-                  int64_t Jpad, void *out, hipStream_t s)
+template <Eng E, int NJT, bool HASH>
+hipError_t launch_one(const ASrc &src, const double2 *Psi, int64_t n, int64_t UM, int64_t j0,
+                      int64_t J, int64_t Jpad, void *out, hipStream_t s)
 {
     const int64_t npad32 = (n + 31) / 32 * 32;
     const size_t shm = size_t(npad32 * Jpad) * sizeof(typename EngT<E>::cplx);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&psi_a_mfma<E, NJT>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&psi_a_mfma<E, NJT, HASH>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
+    // Generation costs ~40 integer ops per entry: more workgroups to hide it.
     int64_t tiles = (UM + 63) / 64;
-    if (tiles > 1024) tiles = 1024;
-    hipLaunchKernelGGL((psi_a_mfma<E, NJT>), dim3(unsigned(tiles)), dim3(kThreads), shm, s, A, Psi,
-                       n, UM, j0, J, Jpad, out);
+    const int64_t cap = HASH ? 4096 : 1024;
+    if (tiles > cap) tiles = cap;
+    hipLaunchKernelGGL((psi_a_mfma<E, NJT, HASH>), dim3(unsigned(tiles)), dim3(kThreads), shm, s,
+                       src, Psi, n, UM, j0, J, Jpad, out);
     return hipGetLastError();
+}
+
+template <Eng E, int NJT>
+hipError_t launch(const ASrc &src, bool hashed, const double2 *Psi, int64_t n, int64_t UM,
+                  int64_t j0, int64_t J, int64_t Jpad, void *out, hipStream_t s)
+{
+    if (hashed) return launch_one<E, NJT, true>(src, Psi, n, UM, j0, J, Jpad, out, s);
+    return launch_one<E, NJT, false>(src, Psi, n, UM, j0, J, Jpad, out, s);
 }
 
 }  // namespace
@@ -105,8 +128,10 @@ hipError_t launch_psi_a_mfma(const ChainArgs &a)
     void *dst = a.ws + p.lay.buf[0];
     const double2 *Psi = reinterpret_cast<const double2 *>(a.U);
     const int njt = int(p.Jpad / 16);
-#define NPF_PSI_CASE(E_, K_)                                                                \
-    if (njt == K_) return launch<E_, K_>(a.A->values, Psi, p.n, UM, a.j0, a.J, p.Jpad, dst, \
+    const ASrc src{a.A->values, a.A->seed, a.A->scale, a.M};
+    const bool hashed = a.A->kind == NPF_SRC_HASH;
+#define NPF_PSI_CASE(E_, K_)                                                                 \
+    if (njt == K_) return launch<E_, K_>(src, hashed, Psi, p.n, UM, a.j0, a.J, p.Jpad, dst, \
                                          a.stream);
     if (p.prec == NPF_FP64) {
         NPF_PSI_CASE(Eng::F64, 1) NPF_PSI_CASE(Eng::F64, 2) NPF_PSI_CASE(Eng::F64, 3)

@@ -14,6 +14,11 @@ that is symmetric in (a1..aM), entry (k, sorted tuple t_1 <= ... <= t_M) lives a
 derivative value (the Taylor coefficient times M!), matching eq. (1) read as a
 derivative expansion and Alg. 2 step 4, which divides by N!.
 
+Hash-generated tensors: for systems too large to store, A_M is defined by a counter-based
+generator instead of stored values (see ``hash_value``); the GPU library generates the
+entries it needs on the device and the CPU oracle generates them on the host, each from
+the generator's published definition.  The numpy version here materialises small cases.
+
 The workloads follow the paper's setting (Section III: power-system models of 6 to
 4251 states, orders 2 to 4).  The paper's systems are not available, so seeded
 stand-ins of the same shapes are generated; the recipe of each is stated in the
@@ -24,7 +29,7 @@ from __future__ import annotations
 import dataclasses
 import itertools
 import math
-from typing import Dict, List, Optional
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -64,6 +69,7 @@ class System:
     A1    float64    [n, n]     Jacobian, Re(V diag(lam) U)
     A     {M: float64 [n, binom(n+M-1, M)]}  packed derivative tensors, M >= 2
     support {M: int64 [s]}      sorted union of ranks that may be nonzero (None = dense)
+    hashed  {M: (seed, scale)}  orders whose A_M is hash-generated (A[M] is None)
     """
 
     name: str
@@ -77,6 +83,7 @@ class System:
     eps: float = 1e-9
     tau: float = 1e-2
     delta: float = 1.0
+    hashed: Dict[int, Tuple[int, float]] = dataclasses.field(default_factory=dict)
 
     @property
     def orders(self) -> List[int]:
@@ -220,6 +227,67 @@ def resonant_system(n: int, orders, seed: int, n_res2: int = 4, n_res3: int = 4,
     return _finish(name, n, lam, V, A, {M: None for M in A}, **kw)
 
 
+# ----------------------------------------------------------------------------- hash tensors
+SPLITMIX_GAMMA = 0x9E3779B97F4A7C15
+HASH_SQRT3 = 1.7320508075688772
+
+
+def hash_counter(M: int, k, r):
+    """Counter of entry (order M, state k, colex rank r): (M << 49) | (k << 40) | r.
+    Valid for M < 8, k < 512 and r < 2^40."""
+    return (np.uint64(M) << np.uint64(49)) | (np.asarray(k, dtype=np.uint64) << np.uint64(40)) \
+        | np.asarray(r, dtype=np.uint64)
+
+
+def splitmix64(seed: int, idx) -> np.ndarray:
+    """Output number ``idx`` (0-based) of SplitMix64 started at ``seed`` (Steele, Lea and
+    Flood, OOPSLA 2014): z = seed + (idx + 1) * gamma, then the variant-13 finaliser
+    z ^= z >> 30; z *= 0xBF58476D1CE4E5B9; z ^= z >> 27; z *= 0x94D049BB133111EB;
+    z ^= z >> 31 (all mod 2^64)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(idx, dtype=np.uint64) + np.uint64(1)) * np.uint64(SPLITMIX_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def hash_value(seed: int, scale: float, M: int, k, r) -> np.ndarray:
+    """Entry A_M[k, r] of a hash-generated tensor.
+
+    w = splitmix64(seed, counter(M, k, r)); its four 16-bit fields f_q give four uniforms
+    (f_q + 1/2) / 2^16 whose sum minus 2 has mean 0 and variance 1/3 (Irwin-Hall), so
+    x = (S - 131070) * 2^-16 with S = f_0 + f_1 + f_2 + f_3 (exact), and
+    A = (x * sqrt(3)) * scale with two IEEE roundings in that order.  No transcendental
+    function is involved, so every implementation reproduces the bits."""
+    w = splitmix64(seed, hash_counter(M, k, r))
+    S = np.zeros(w.shape, dtype=np.int64)
+    for q in range(4):
+        S += ((w >> np.uint64(16 * q)) & np.uint64(0xFFFF)).astype(np.int64)
+    x = (S - 131070).astype(np.float64) * 2.0 ** -16
+    return (x * HASH_SQRT3) * np.float64(scale)
+
+
+def hash_tensor(n: int, M: int, seed: int, scale: float) -> np.ndarray:
+    """Packed [n, binom(n+M-1, M)] materialisation of a hash-generated tensor (small n)."""
+    U = n_sorted(n, M)
+    k = np.repeat(np.arange(n, dtype=np.uint64), U)
+    r = np.tile(np.arange(U, dtype=np.uint64), n)
+    return hash_value(seed, scale, M, k, r).reshape(n, U)
+
+
+def hash_system(n: int, orders, seed: int, name: str = "hash", materialize: bool = False,
+                **kw) -> System:
+    """Dense system whose A_M are hash-generated with scale n^(-M/2) and generator seed
+    ``seed + M``; spectrum and eigenvectors as for the other systems.  With
+    ``materialize`` the packed tensors are also built (small n only)."""
+    rng = np.random.default_rng(seed)
+    lam = _spectrum(n, rng)
+    V = _eigvecs(n, rng)
+    hashed = {M: (int(seed + M), float(n) ** (-M / 2.0)) for M in orders if M >= 2}
+    A = {M: (hash_tensor(n, M, *hashed[M]) if materialize else None) for M in hashed}
+    return _finish(name, n, lam, V, A, {M: None for M in A}, hashed=hashed, **kw)
+
+
 # ----------------------------------------------------------------------------- workloads
 def workload_small() -> System:
     """n=10, orders 1-2: five conjugate pairs, dense A2 ~ N(0,1)/n."""
@@ -236,6 +304,12 @@ def workload_dense128() -> System:
     return resonant_system(128, [2, 3, 4], BASE_SEED + 2, name="n128-o4-dense-resonant")
 
 
+def workload_hash200() -> System:
+    """n=200, orders 2-4, dense A_M ~ Irwin-Hall(4) / n^(M/2), hash-generated (A_4 alone
+    would be 110 GB in FP64)."""
+    return hash_system(200, [2, 3, 4], BASE_SEED + 4, name="n200-o4-dense-hash")
+
+
 def workload_batch(count: int = 256, seed: int = BASE_SEED + 3) -> List[System]:
     """``count`` block-sparse systems, n uniform over even values in [32, 160], orders 2-3."""
     rng = np.random.default_rng(seed)
@@ -248,6 +322,7 @@ WORKLOADS = {
     "n10-o2-dense": workload_small,
     "n64-o3-blocksparse": workload_sparse64,
     "n128-o4-dense-resonant": workload_dense128,
+    "n200-o4-dense-hash": workload_hash200,
 }
 
 

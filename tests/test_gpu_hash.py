@@ -1,0 +1,112 @@
+"""Hash-generated derivative tensors and the kernel shapes for 65 to 256 states, on the GPU
+through the C ABI.
+
+- npf_hash_fill reproduces the generator's definition bit for bit;
+- a hash-generated tensor gives bitwise the same NPFs as the same tensor stored;
+- systems of 100 to 250 states, with output-mode blocks of 16 and 32 modes (several items
+  per workgroup) and with the reduction's states split over workgroups (n > 128), match
+  the oracle on sampled modes (P rows and NPF columns);
+- the n=200, orders 2-4 hash-generated workload at full size matches the stored oracle
+  values of its sampled modes.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_08968_amd import binding as B
+from paper_2509_08968_amd import inputs as I
+from tests.helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6}
+GOLD200 = os.path.join(os.path.dirname(__file__), "golden", "hash200_modes.json")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+    return torch, "cuda:0"
+
+
+@pytest.mark.parametrize("n,M,k0,k1", [(37, 2, 0, 37), (200, 3, 5, 7), (9, 6, 0, 9), (200, 4, 199, 200)])
+def test_hash_fill_bitwise(torch_dev, n, M, k0, k1):
+    torch, dev = torch_dev
+    print(f"[hash fill] n={n} M={M} rows {k0}:{k1}", flush=True)
+    seed, scale = 977 + M, float(n) ** (-M / 2.0)
+    U = math.comb(n + M - 1, M)
+    out = torch.empty((k1 - k0) * U, dtype=torch.float64, device=dev)
+    B.hash_fill(n, M, seed, scale, k0, k1, out)
+    torch.cuda.synchronize()
+    k = np.repeat(np.arange(k0, k1, dtype=np.uint64), U)
+    r = np.tile(np.arange(U, dtype=np.uint64), k1 - k0)
+    want = I.hash_value(seed, scale, M, k, r)
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_hash_source_equals_stored_tensor(torch_dev, precision):
+    s = I.hash_system(24, [2, 3, 4], 4501, materialize=True)
+    print(f"[hash vs stored {precision}] n=24", flush=True)
+    a, Pa = B.compute(s, precision, hash_source=True)
+    b, Pb = B.compute(s, precision, hash_source=False)
+    for M in s.orders:
+        assert np.array_equal(Pa[M], Pb[M]), M
+    assert np.array_equal(a, b)
+    ref = {M: oracle.sym(s, M)["P"] for M in s.orders}
+    for M in s.orders:
+        assert rel(Pa[M], ref[M]) <= TOL[precision], M
+
+
+# name -> (builder, output modes per block or 0 for the planner's choice, precisions)
+LARGE_CASES = {
+    "n100-o3-dense-J16": (lambda: I.dense_system(100, [2, 3], 4601), 16, ["bf16x3", "fp64"]),
+    "n100-o3-dense-J32": (lambda: I.dense_system(100, [2, 3], 4601), 32, ["bf16x3"]),
+    "n150-o3-dense": (lambda: I.dense_system(150, [2, 3], 4602), 0, ["bf16x3", "fp32"]),
+    "n200-o3-hash-J16": (lambda: I.hash_system(200, [2, 3], 4603), 16, ["bf16x3"]),
+    "n250-o3-dense": (lambda: I.dense_system(250, [2, 3], 4604), 0, ["bf16x3"]),
+    "n100-o4-hash-J48": (lambda: I.hash_system(100, [2, 3, 4], 4605), 48, ["bf16x3"]),
+}
+LARGE_PARAMS = [(c, p) for c, (_, _, ps) in sorted(LARGE_CASES.items()) for p in ps]
+
+
+def _sampled(s, ref_modes, precision, block_modes, budget=0):
+    ref = {M: oracle.sym(s, M, modes=ref_modes)["P"] for M in s.orders}
+    npf, Ps = B.compute(s, precision, block_modes=block_modes, budget_bytes=budget)
+    for M in s.orders:
+        assert rel(Ps[M][ref_modes], ref[M]) <= TOL[precision], f"P_{M}"
+    z = np.stack([s.delta * s.U[i, :] for i in ref_modes])
+    npf_cols = s.V[:, ref_modes] * (z + sum(ref.values())).T
+    assert rel(npf[:, ref_modes], npf_cols) <= TOL[precision], "NPF"
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("case,precision", LARGE_PARAMS)
+def test_large_n_sampled_modes(torch_dev, case, precision):
+    build, bm, _ = LARGE_CASES[case]
+    s = build()
+    modes = sorted({0, s.n // 2 + 1, s.n - 1})
+    print(f"[large {precision}] {case} modes {modes}", flush=True)
+    _sampled(s, modes, precision, bm)
+
+
+@pytest.mark.timeout(900)
+def test_workload_n200_o4_hash_sampled(torch_dev):
+    """n=200, orders 2-4, dense hash-generated tensors (never stored), 96 GiB workspace
+    budget (13 blocks of 16 output modes); P rows and NPF columns of the sampled modes
+    against the oracle values stored by tests/golden/make_hash200_golden.py."""
+    g = json.load(open(GOLD200))
+    s = I.workload_hash200()
+    modes = g["modes"]
+    print(f"[n200-o4-hash bf16x3] modes {modes}", flush=True)
+    npf, Ps = B.compute(s, "bf16x3", budget_bytes=96 << 30)
+    cplx = lambda a: np.asarray(a)[..., 0] + 1j * np.asarray(a)[..., 1]
+    for M in s.orders:
+        assert rel(Ps[M][modes], cplx(g["P"][str(M)])) <= TOL["bf16x3"], f"P_{M}"
+    assert rel(npf[:, modes], cplx(g["npf_columns"]).T) <= TOL["bf16x3"], "NPF"

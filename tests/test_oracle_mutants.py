@@ -27,8 +27,8 @@ MUTANTS = {
                              "acc[t] = acc[t] + x * Phi[t * n + a];"),
     "Phi transposed (full)": ("s = s + T[(o * n + a) * inner + in] * Phi[a * n + tp];",
                               "s = s + T[(o * n + a) * inner + in] * Phi[tp * n + a];"),
-    "Psi transposed in G": ("for (int64_t k = 0; k < n; ++k) s = s + Psi[j * n + k] * A_packed[k * UM + r];",
-                            "for (int64_t k = 0; k < n; ++k) s = s + Psi[k * n + j] * A_packed[k * UM + r];"),
+    "Psi transposed in G": ("                s = s + Psi[j * n + k] * a;",
+                            "                s = s + Psi[k * n + j] * a;"),
     "multiplicity dropped": ("s = s + multiplicity(t, M) * (h[r] * z);", "s = s + (h[r] * z);"),
     "delta dropped in zeta": ("npfo_c z = delta * Psi[t[0] * n + k];", "npfo_c z = Psi[t[0] * n + k];"),
     "zeta index transposed": ("z = z * (delta * Psi[t[l] * n + k]);", "z = z * (delta * Psi[k * n + t[l]]);"),
