@@ -95,25 +95,25 @@ fused_bf3(Bf3Args a)
         const double w_gt = -1.0 / den, w_eq = -1.0 / (den * double(run + 1));
         const float w_gt_f = float(w_gt), w_eq_f = float(w_eq);
 
-        v4f rr[NKT], ri[NKT];
+        v4f rr[NKT], ri[NKT], rrl[NKT], ril[NKT];
 #pragma unroll
-        for (int kt = 0; kt < NKT; ++kt) rr[kt] = ri[kt] = v4f{0, 0, 0, 0};
+        for (int kt = 0; kt < NKT; ++kt) rr[kt] = ri[kt] = rrl[kt] = ril[kt] = v4f{0, 0, 0, 0};
 
         for (int tc = m / 32; tc < KC; ++tc) {
             const int t0 = tc * 32;
-            v4f sr[2], si[2];
+            v4f sr[2], si[2], srl[2], sil[2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) sr[u] = si[u] = v4f{0, 0, 0, 0};
+            for (int u = 0; u < 2; ++u) sr[u] = si[u] = srl[u] = sil[u] = v4f{0, 0, 0, 0};
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     Split3 pr, pi;
                     phi_frags<NP>(Lphi, kc * 32, t0 + 16 * u + c, g, pr, pi);
-                    sr[u] = mm6(pr, xr[kc], sr[u]);
-                    sr[u] = mm6(pi, xn_[kc], sr[u]);
-                    si[u] = mm6(pr, xi[kc], si[u]);
-                    si[u] = mm6(pi, xr[kc], si[u]);
+                    mm6s(pr, xr[kc], sr[u], srl[u]);
+                    mm6s(pi, xn_[kc], sr[u], srl[u]);
+                    mm6s(pr, xi[kc], si[u], sil[u]);
+                    mm6s(pi, xr[kc], si[u], sil[u]);
                 }
             // Divisor and division (FP64 divisor) into the A operand of the reduction.
             float hre[8], him[8];
@@ -130,7 +130,7 @@ fused_bf3(Bf3Args a)
                     const float dx = float(d.x), dy = float(d.y);
                     const float dd = dx * dx + dy * dy;
                     const float w = (t == m) ? w_eq_f : w_gt_f;
-                    const float sx = sr[u][r], sy = si[u][r];
+                    const float sx = sr[u][r] + srl[u][r], sy = si[u][r] + sil[u][r];
                     if (dd < guard) {
                         const double2 dc = divisor_fp64(acc, lam_j, a.eps);
                         const double f = ((t == m) ? w_eq : w_gt) / (dc.x * dc.x + dc.y * dc.y);
@@ -157,10 +157,10 @@ fused_bf3(Bf3Args a)
                 Split3 zr_, zi_;
                 zr_.h = ld(0); zr_.m = ld(1); zr_.l = ld(2);
                 zi_.h = ld(3); zi_.m = ld(4); zi_.l = ld(5);
-                rr[kt] = mm6(ar_, zr_, rr[kt]);
-                rr[kt] = mm6(an_, zi_, rr[kt]);
-                ri[kt] = mm6(ar_, zi_, ri[kt]);
-                ri[kt] = mm6(ai_, zr_, ri[kt]);
+                mm6s(ar_, zr_, rr[kt], rrl[kt]);
+                mm6s(an_, zi_, rr[kt], rrl[kt]);
+                mm6s(ar_, zi_, ri[kt], ril[kt]);
+                mm6s(ai_, zr_, ri[kt], ril[kt]);
             }
         }
         // P += zp * R in FP64, zp[k] = prod_i zeta[p_i][k].
@@ -177,7 +177,7 @@ fused_bf3(Bf3Args a)
             // items is kept in FP64.
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float vr = rr[kt][r], vi = ri[kt][r];
+                const float vr = rr[kt][r] + rrl[kt][r], vi = ri[kt][r] + ril[kt][r];
                 pacc_r[kt][r] += double(vr * z.x - vi * z.y);
                 pacc_i[kt][r] += double(vr * z.y + vi * z.x);
             }

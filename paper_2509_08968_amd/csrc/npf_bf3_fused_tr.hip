@@ -15,7 +15,7 @@ namespace {
 // block, the four waves take IPW = 4 / tiles items at once (item slot = wave / (4 / IPW)),
 // each slot writing its own partial.  For NP > 128 the states k of the reduction are split
 // in KS ranges over grid.y (the first product is recomputed per range) so that the FP64
-// accumulators and the zeta slice fit.
+// accumulators fit in registers and the zeta slice in LDS.
 template <int NP, int M, int IPW, int KS>
 __global__ void __launch_bounds__(kThreads)
 fused_bf3_tr(Bf3Args a)
@@ -131,9 +131,9 @@ fused_bf3_tr(Bf3Args a)
         }
 
         // GEMM1 over the slice's two t-tiles, rows loaded one K-chunk ahead.
-        v4f sr[2], si[2];
+        v4f sr[2], si[2], srl[2], sil[2];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) sr[u] = si[u] = v4f{0, 0, 0, 0};
+        for (int u = 0; u < 2; ++u) sr[u] = si[u] = srl[u] = sil[u] = v4f{0, 0, 0, 0};
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
             float2 nxt[8];
@@ -152,10 +152,10 @@ fused_bf3_tr(Bf3Args a)
                 pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PLP + pidx);
                 pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PLP + pidx);
                 pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PLP + pidx);
-                sr[u] = mm6(pr, xr, sr[u]);
-                sr[u] = mm6(pi, xng, sr[u]);
-                si[u] = mm6(pr, xi, si[u]);
-                si[u] = mm6(pi, xr, si[u]);
+                mm6s(pr, xr, sr[u], srl[u]);
+                mm6s(pi, xng, sr[u], srl[u]);
+                mm6s(pr, xi, si[u], sil[u]);
+                mm6s(pi, xr, si[u], sil[u]);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
@@ -173,7 +173,7 @@ fused_bf3_tr(Bf3Args a)
                 const float dx = float(d.x), dy = float(d.y);
                 const float dd = dx * dx + dy * dy;
                 const float w = (t == m) ? w_eq_f : w_gt_f;
-                const float sx = sr[u][r], sy = si[u][r];
+                const float sx = sr[u][r] + srl[u][r], sy = si[u][r] + sil[u][r];
                 if (dd < guard) {
                     const double2 dc = divisor_fp64(acc, lam_j, a.eps);
                     const double f = ((t == m) ? w_eq : w_gt) / (dc.x * dc.x + dc.y * dc.y);
@@ -204,14 +204,15 @@ fused_bf3_tr(Bf3Args a)
             zi_.m = *reinterpret_cast<const v8bf *>(Lz + 4 * PLZ + z0);
             zi_.l = *reinterpret_cast<const v8bf *>(Lz + 5 * PLZ + z0);
             v4f rr = v4f{0, 0, 0, 0}, ri = v4f{0, 0, 0, 0};
-            rr = mm6(ar_, zr_, rr);
-            rr = mm6(an_, zi_, rr);
-            ri = mm6(ar_, zi_, ri);
-            ri = mm6(ai_, zr_, ri);
+            v4f rrl = v4f{0, 0, 0, 0}, ril = v4f{0, 0, 0, 0};
+            mm6s(ar_, zr_, rr, rrl);
+            mm6s(an_, zi_, rr, rrl);
+            mm6s(ar_, zi_, ri, ril);
+            mm6s(ai_, zr_, ri, ril);
             const float2 z = zp[kt];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float vr = rr[r], vi = ri[r];
+                const float vr = rr[r] + rrl[r], vi = ri[r] + ril[r];
                 pacc_r[kt][r] += double(vr * z.x - vi * z.y);
                 pacc_i[kt][r] += double(vr * z.y + vi * z.x);
             }
@@ -261,13 +262,13 @@ hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J
     a.M = M;
     const int NP = int(p->npad);
     const int ipw = bf3_items_per_group(p->Jpad);
-    const int ks = NP > 128 ? 2 : 1;
+    const int ks = NP > 224 ? 4 : (NP > 128 ? 2 : 1);
     const int64_t jgroups = (p->Jpad / 16 * ipw + 3) / 4;
     const dim3 grid{unsigned(groups), unsigned(jgroups * ks), unsigned(NP / 32)};
     const size_t shm = size_t(12 * NP * 32 + 12 * 32 * (NP / ks) + 16 * NP);
 #define NPF_FUSED_TR(NP_, M_, IPW_)                                                             \
     if (NP == NP_ && M == M_ && ipw == IPW_) {                                                 \
-        constexpr int KS_ = NP_ > 128 ? 2 : 1;                                                 \
+        constexpr int KS_ = NP_ > 224 ? 4 : (NP_ > 128 ? 2 : 1);                               \
         set_lds_limit(fused_bf3_tr<NP_, M_, IPW_, KS_>, int(shm));                              \
         hipLaunchKernelGGL((fused_bf3_tr<NP_, M_, IPW_, KS_>), grid, dim3(kThreads), shm, s, a); \
         return hipGetLastError();                                                               \

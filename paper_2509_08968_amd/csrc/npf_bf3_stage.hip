@@ -85,9 +85,9 @@ stage_bf3(Bf3Args a)
         if (a.i > 1) m = int((a.ptab[rp] >> (8 * (a.i - 2))) & 0xff);
         const int tt0 = m / 16;
 
-        v4f sr[NTT], si[NTT];
+        v4f sr[NTT], si[NTT], srl[NTT], sil[NTT];
 #pragma unroll
-        for (int tt = 0; tt < NTT; ++tt) sr[tt] = si[tt] = v4f{0, 0, 0, 0};
+        for (int tt = 0; tt < NTT; ++tt) sr[tt] = si[tt] = srl[tt] = sil[tt] = v4f{0, 0, 0, 0};
 #pragma unroll
         for (int tt = 0; tt < NTT; ++tt) {
             if (tt < tt0) continue;
@@ -95,10 +95,10 @@ stage_bf3(Bf3Args a)
             for (int kc = 0; kc < KC; ++kc) {
                 Split3 pr, pi;
                 phi_frags<NP>(Lphi, kc * 32, tt * 16 + c, g, pr, pi);
-                sr[tt] = mm6(pr, xr[kc], sr[tt]);
-                sr[tt] = mm6(pi, xn_[kc], sr[tt]);
-                si[tt] = mm6(pr, xi[kc], si[tt]);
-                si[tt] = mm6(pi, xr[kc], si[tt]);
+                mm6s(pr, xr[kc], sr[tt], srl[tt]);
+                mm6s(pi, xn_[kc], sr[tt], srl[tt]);
+                mm6s(pr, xi[kc], si[tt], sil[tt]);
+                mm6s(pi, xr[kc], si[tt], sil[tt]);
             }
         }
         // Row rank(p U t) = rp + binom(t + i - 1, i).
@@ -111,7 +111,7 @@ stage_bf3(Bf3Args a)
             for (int r = 0; r < 4; ++r) {
                 const int t = tt * 16 + 4 * g + r;
                 if (t < m || t >= nn) continue;
-                dst[rowoff[t]] = make_float2(sr[tt][r], si[tt][r]);
+                dst[rowoff[t]] = make_float2(sr[tt][r] + srl[tt][r], si[tt][r] + sil[tt][r]);
             }
         }
     }

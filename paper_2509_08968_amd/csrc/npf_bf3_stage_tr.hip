@@ -108,12 +108,12 @@ stage_bf3_tr(Bf3Args a)
             continue;
         }
         const int tt0 = (m > t_base) ? (m - t_base) / 16 : 0;
-        v4f sr[TT], si[TT];
+        v4f sr[TT], si[TT], srl[TT], sil[TT];
         // Straight-line tile loops for each first active tile (no branches between MFMAs).
         auto sweep = [&](auto first) {
             constexpr int T0 = decltype(first)::value;
 #pragma unroll
-            for (int tt = 0; tt < TT; ++tt) sr[tt] = si[tt] = v4f{0, 0, 0, 0};
+            for (int tt = 0; tt < TT; ++tt) sr[tt] = si[tt] = srl[tt] = sil[tt] = v4f{0, 0, 0, 0};
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
                 float2 nxt[8];
@@ -132,10 +132,10 @@ stage_bf3_tr(Bf3Args a)
                     pi.h = *reinterpret_cast<const v8bf *>(Lphi + 3 * PL + pidx);
                     pi.m = *reinterpret_cast<const v8bf *>(Lphi + 4 * PL + pidx);
                     pi.l = *reinterpret_cast<const v8bf *>(Lphi + 5 * PL + pidx);
-                    sr[tt] = mm6(pr, xr, sr[tt]);
-                    sr[tt] = mm6(pi, xng, sr[tt]);
-                    si[tt] = mm6(pr, xi, si[tt]);
-                    si[tt] = mm6(pi, xr, si[tt]);
+                    mm6s(pr, xr, sr[tt], srl[tt]);
+                    mm6s(pi, xng, sr[tt], srl[tt]);
+                    mm6s(pr, xi, si[tt], sil[tt]);
+                    mm6s(pi, xr, si[tt], sil[tt]);
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
@@ -157,7 +157,7 @@ stage_bf3_tr(Bf3Args a)
                 const int tl = tt * 16 + 4 * g + r;
                 const int t = t_base + tl;
                 if (t < m || t >= nn) continue;
-                dst[rowoff[tl]] = make_float2(sr[tt][r], si[tt][r]);
+                dst[rowoff[tl]] = make_float2(sr[tt][r] + srl[tt][r], si[tt][r] + sil[tt][r]);
             }
         }
     }

@@ -90,6 +90,21 @@ __device__ __forceinline__ v4f mm6(const Split3 &a, const Split3 &b, v4f c)
     return c;
 }
 
+// mm6 with the sum kept in two parts: the hi*hi product goes to `hi`, the five smaller
+// products (at most 2^-7 of it) to `lo`.  A BF16 MFMA adds the exact sum of its products
+// to the accumulator with one rounding to nearest, so `hi` takes one rounding per
+// product pair instead of six and the roundings of `lo` are 2^-8 smaller; the caller
+// forms hi + lo once at the end.
+__device__ __forceinline__ void mm6s(const Split3 &a, const Split3 &b, v4f &hi, v4f &lo)
+{
+    lo = mfma(a.h, b.l, lo);
+    lo = mfma(a.l, b.h, lo);
+    lo = mfma(a.m, b.m, lo);
+    lo = mfma(a.h, b.m, lo);
+    lo = mfma(a.m, b.h, lo);
+    hi = mfma(a.h, b.h, hi);
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Position of zeta[t][k] in a BF16 plane laid out so that the reduction's B fragment of

@@ -2,9 +2,10 @@
 // first):  T_0[r][jj] = sum_k A_M[k][r] Psi[j0 + jj][k]  for every sorted tuple r.
 // A_M is real and read once per output-mode block, so the kernel is bound by the HBM
 // stream of A_M; Psi^T for the block (n x Jpad complex) stays in LDS for the whole launch
-// and each workgroup sweeps 64-row tiles of r.  FP64 MFMA for the FP64 path, FP32 MFMA
-// (FP32 accumulation) for the FP32 and split-BF16 paths.  For a hash-generated tensor the
-// A_M entries are generated in registers where the stored ones would be loaded.
+// and each workgroup sweeps 64-row tiles of r.  FP64 MFMA for the FP64 and split-BF16
+// paths (the split path stores the result in FP32: one rounding of an FP64 sum over the n
+// states), FP32 MFMA for the FP32 path.  For a hash-generated tensor the A_M entries are
+// generated in registers where the stored ones would be loaded.
 #include "npf_device.h"
 #include "npf_internal.h"
 #include "npf_mfma.h"
@@ -23,7 +24,7 @@ struct ASrc {
     int M;
 };
 
-template <Eng E, int NJT, bool HASH>
+template <Eng E, int NJT, bool HASH, typename OutC>
 __global__ void __launch_bounds__(kThreads)
 psi_a_mfma(ASrc src, const double2 *__restrict__ Psi, int64_t n, int64_t UM, int64_t j0,
            int64_t J, int64_t Jpad, void *__restrict__ out_)
@@ -44,7 +45,8 @@ psi_a_mfma(ASrc src, const double2 *__restrict__ Psi, int64_t n, int64_t UM, int
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
-    cplx *out = static_cast<cplx *>(out_);
+    OutC *out = static_cast<OutC *>(out_);
+    using out_real = decltype(OutC{}.x);
     for (int64_t r0 = int64_t(blockIdx.x) * 64 + wave * 16; r0 < UM; r0 += int64_t(gridDim.x) * 64) {
         const int64_t r = r0 + c;
         const bool r_ok = r < UM;
@@ -81,34 +83,35 @@ psi_a_mfma(ASrc src, const double2 *__restrict__ Psi, int64_t n, int64_t UM, int
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t rr = r0 + out_row<E>(q, g);
-                if (rr < UM) out[rr * Jpad + u * 16 + c] = cplx{ar[u][q], ai[u][q]};
+                if (rr < UM)
+                    out[rr * Jpad + u * 16 + c] = OutC{out_real(ar[u][q]), out_real(ai[u][q])};
             }
     }
 }
 
-template <Eng E, int NJT, bool HASH>
+template <Eng E, int NJT, bool HASH, typename OutC>
 hipError_t launch_one(const ASrc &src, const double2 *Psi, int64_t n, int64_t UM, int64_t j0,
                       int64_t J, int64_t Jpad, void *out, hipStream_t s)
 {
     const int64_t npad32 = (n + 31) / 32 * 32;
     const size_t shm = size_t(npad32 * Jpad) * sizeof(typename EngT<E>::cplx);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&psi_a_mfma<E, NJT, HASH>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&psi_a_mfma<E, NJT, HASH, OutC>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, int(shm));
     // Generation costs ~40 integer ops per entry: more workgroups to hide it.
     int64_t tiles = (UM + 63) / 64;
     const int64_t cap = HASH ? 4096 : 1024;
     if (tiles > cap) tiles = cap;
-    hipLaunchKernelGGL((psi_a_mfma<E, NJT, HASH>), dim3(unsigned(tiles)), dim3(kThreads), shm, s,
-                       src, Psi, n, UM, j0, J, Jpad, out);
+    hipLaunchKernelGGL((psi_a_mfma<E, NJT, HASH, OutC>), dim3(unsigned(tiles)), dim3(kThreads),
+                       shm, s, src, Psi, n, UM, j0, J, Jpad, out);
     return hipGetLastError();
 }
 
-template <Eng E, int NJT>
+template <Eng E, int NJT, typename OutC = typename EngT<E>::cplx>
 hipError_t launch(const ASrc &src, bool hashed, const double2 *Psi, int64_t n, int64_t UM,
                   int64_t j0, int64_t J, int64_t Jpad, void *out, hipStream_t s)
 {
-    if (hashed) return launch_one<E, NJT, true>(src, Psi, n, UM, j0, J, Jpad, out, s);
-    return launch_one<E, NJT, false>(src, Psi, n, UM, j0, J, Jpad, out, s);
+    if (hashed) return launch_one<E, NJT, true, OutC>(src, Psi, n, UM, j0, J, Jpad, out, s);
+    return launch_one<E, NJT, false, OutC>(src, Psi, n, UM, j0, J, Jpad, out, s);
 }
 
 }  // namespace
@@ -117,7 +120,7 @@ bool psi_a_mfma_supported(const npf_plan_s *p)
 {
     // Psi^T of the block must fit in LDS and the block must be at most 128 modes.
     const int64_t npad32 = (p->n + 31) / 32 * 32;
-    const int64_t bytes = npad32 * p->Jpad * (p->prec == NPF_FP64 ? 16 : 8);
+    const int64_t bytes = npad32 * p->Jpad * (p->prec == NPF_FP32 ? 8 : 16);
     return p->Jpad <= 128 && bytes <= 144 * 1024;
 }
 
@@ -137,6 +140,13 @@ hipError_t launch_psi_a_mfma(const ChainArgs &a)
         NPF_PSI_CASE(Eng::F64, 1) NPF_PSI_CASE(Eng::F64, 2) NPF_PSI_CASE(Eng::F64, 3)
         NPF_PSI_CASE(Eng::F64, 4) NPF_PSI_CASE(Eng::F64, 5) NPF_PSI_CASE(Eng::F64, 6)
         NPF_PSI_CASE(Eng::F64, 7) NPF_PSI_CASE(Eng::F64, 8)
+    } else if (p.prec == NPF_BF16X3) {
+#define NPF_PSI_CASE64(K_)                                                                   \
+    if (njt == K_) return launch<Eng::F64, K_, float2>(src, hashed, Psi, p.n, UM, a.j0, a.J, \
+                                                       p.Jpad, dst, a.stream);
+        NPF_PSI_CASE64(1) NPF_PSI_CASE64(2) NPF_PSI_CASE64(3) NPF_PSI_CASE64(4)
+        NPF_PSI_CASE64(5) NPF_PSI_CASE64(6) NPF_PSI_CASE64(7) NPF_PSI_CASE64(8)
+#undef NPF_PSI_CASE64
     } else {
         NPF_PSI_CASE(Eng::F32, 1) NPF_PSI_CASE(Eng::F32, 2) NPF_PSI_CASE(Eng::F32, 3)
         NPF_PSI_CASE(Eng::F32, 4) NPF_PSI_CASE(Eng::F32, 5) NPF_PSI_CASE(Eng::F32, 6)
