@@ -215,6 +215,143 @@ def cpu_baseline(s, entries, target_s=10.0):
                       f"{el:.1f} s, packed-symmetric FP64 oracle with {cores} OpenMP threads"}
 
 
+BATCH_WORKLOAD = "batch256-o3-blocksparse"
+BATCH_BUDGET = 128 << 30
+
+
+def bench_batch(args):
+    """256 block-sparse systems (n uniform over even values in [32, 160], orders 2-3) in one
+    batched call per step, replayed as a graph; per-system solo rates beside it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2509_08968_amd import binding as B
+    from paper_2509_08968_amd import inputs as I
+
+    device = "cuda:0"
+    torch.cuda.set_device(0)
+    B.lib()
+    t0 = time.perf_counter()
+    ss = I.workload_batch()
+    devs = [B.upload_system(s, device) for s in ss]
+    log(f"[bench] {len(ss)} systems generated and uploaded in {time.perf_counter() - t0:.1f} s")
+    b = B.Batch(ss, BATCH_BUDGET)
+    ws = b.workspace(device)
+    P = [torch.empty((s.order_max - 1, s.n, s.n), dtype=torch.complex128, device=device) for s in ss]
+    N = [torch.empty((s.n, s.n), dtype=torch.complex128, device=device) for s in ss]
+    st = torch.cuda.Stream(device=device)
+    tuned = None
+    if not args.no_tune:
+        tuned = b.tune(devs, ws, P, N, st)
+    for _ in range(max(1, args.warmup)):
+        b.run(devs, ws, P, N, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        b.run(devs, ws, P, N, st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    entries = b.report["modal_entries"]
+    value = entries / (ms * 1e-3)
+    log(f"[bench] batch: {ms:.3f} ms/step, {value:.3e} entries/s")
+
+    # Oracle on sampled systems and modes.
+    order = np.argsort([s.n for s in ss], kind="stable")
+    rng = np.random.default_rng(I.BASE_SEED + 3 + 1000)
+    picks = sorted({int(order[0]), int(order[-1]), *[int(x) for x in rng.choice(len(ss), 3, replace=False)]})
+    errs = {}
+    for q in picks:
+        s = ss[q]
+        modes = sorted({0, s.n // 2 + 1, s.n - 1})
+        for M in s.orders:
+            ref = oracle.sym(s, M, modes=modes)["P"]
+            got = P[q][M - 2].cpu().numpy()[modes]
+            errs[f"P{M}"] = max(errs.get(f"P{M}", 0.0), rel(got, ref))
+
+    roof = None
+    if not args.no_profile:
+        launches = b.time_launches(devs, ws, P, N, st)
+        tot = sum(L["ms"] for L in launches)
+        L = max(launches, key=lambda x: x["ms"])
+        achieved = L["flops"] / (L["ms"] * 1e-3) / 1e12
+        name = (f"w{L['wave']}_np{L['npad']}_o{L['order']}_" +
+                (f"stage{L['stage']}" if L["kind"] == 0 else "fused"))
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["bf16x3"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["bf16x3"],
+                "traffic": measured_traffic(BATCH_WORKLOAD, "bf16x3", name),
+                "kernel": name, "systems_in_launch": L["systems"],
+                "workgroups": L["workgroups"], "avg_launch_ms": L["ms"],
+                "algorithmic_flops": L["flops"],
+                "share_of_step": L["ms"] / ms, "shared_launches_ms": tot,
+                "executed_mfma_frac": achieved * SPLIT_PRODUCTS["bf16x3"] / PEAK_TFLOPS["bf16x3"],
+                "timing": "HIP events around every shared launch, one eager run"}
+
+    # Per-system rates: each system alone through npf_run (graph replay), same precision.
+    solo = None
+    if not args.no_solo:
+        big = max(B.Plan(s.n, s.order_max, "bf16x3").workspace_bytes for s in ss)
+        del ws
+        torch.cuda.empty_cache()
+        wsolo = torch.empty(big, dtype=torch.uint8, device=device)
+        rates, total = [], 0.0
+        for q, s in enumerate(ss):
+            plan = B.Plan(s.n, s.order_max, "bf16x3", s.eps, s.tau, s.delta)
+            plan.run(devs[q].tensors, devs[q].U, devs[q].V, devs[q].lam, wsolo, P[q], N[q], st)
+            a, c = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(st)
+            for _ in range(3):
+                plan.run(devs[q].tensors, devs[q].U, devs[q].V, devs[q].lam, wsolo, P[q], N[q], st)
+            c.record(st)
+            torch.cuda.synchronize()
+            t = a.elapsed_time(c) / 3
+            total += t
+            rates.append(plan.modal_entries / (t * 1e-3))
+            plan.close()
+        rates = np.asarray(rates)
+        solo = {"sum_ms": total, "batching_speedup": total / ms,
+                "entries_per_s_min": float(rates.min()), "entries_per_s_median": float(np.median(rates)),
+                "entries_per_s_max": float(rates.max())}
+        log(f"[bench] solo: sum {total:.3f} ms, batching speedup {total / ms:.2f}x")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+        small = [ss[int(i)] for i in order[:24]]
+        t0 = time.perf_counter()
+        done = 0
+        for s in small:
+            for M in s.orders:
+                oracle.sym(s, M, nthreads=cores)
+                done += s.n * math.comb(s.n + M - 1, M)
+        el = time.perf_counter() - t0
+        cpu = {"value": done / el, "unit": "modal entries/s", "cores": cores, "kind": "oracle",
+               "sample": f"the 24 smallest systems of the batch in full (orders 2-3, all modes): "
+                         f"{done} entries in {el:.1f} s, packed-symmetric FP64 oracle with "
+                         f"{cores} OpenMP threads"}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "modal entries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": BATCH_WORKLOAD, "systems": len(ss),
+                   "n_range": [min(s.n for s in ss), max(s.n for s in ss)], "orders": [2, 3],
+                   "precision": "bf16x3", "modal_entries_per_step": entries,
+                   "waves": b.report["waves"], "workspace_bytes": b.report["workspace_bytes"],
+                   "budget_bytes": BATCH_BUDGET, "launches_per_step": b.report["launches"],
+                   "shared_launches": b.report["shared_launches"],
+                   "autotuned_workgroups": tuned, "oracle_checked_systems": picks},
+        "rel_err_vs_oracle": errs,
+        "per_system_solo": solo,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +364,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
+    ap.add_argument("--no-tune", action="store_true", help="batch workload: skip the autotuner")
+    ap.add_argument("--no-solo", action="store_true", help="batch workload: skip per-system runs")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -235,6 +374,9 @@ def main():
               "build (the design for sharding by output mode is described in DESIGN.md).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == BATCH_WORKLOAD:
+        return bench_batch(args)
 
     import numpy as np
     import torch

@@ -139,6 +139,75 @@ int npf_normal_form(npf_plan_t plan, int32_t order, int64_t block, const void *l
 int npf_assemble(npf_plan_t plan, int32_t order, int64_t block, const void *h,
                  const void *U, void *P_acc, void *stream);
 
+/* ---------------------------------------------------------------- batched systems
+ * Many operating points (systems of uneven n, each with its own orders 2..N) through the
+ * whole hot path in one call: the per-step launches of all systems of the same padded
+ * size run as single launches whose workgroups are shared out in proportion to each
+ * system's work; systems run together in waves whose summed workspace fits the budget
+ * (the batching of Alg. 1 applied across systems); the call replays one captured graph.
+ * Split-BF16 precision only (problems[s].precision == NPF_BF16X3), N <= 4, n <= 256; every
+ * system is one block of all its modes. */
+typedef struct npf_batch_s *npf_batch_t;
+
+typedef struct npf_batch_report {
+    int64_t systems;
+    int64_t waves;              /* groups of systems that run together                 */
+    int64_t workspace_bytes;    /* device workspace npf_batch_run needs                 */
+    int64_t modal_entries;      /* sum over systems and orders of n * U_M               */
+    int64_t launches;           /* kernel launches per run                             */
+    int64_t shared_launches;    /* of which launches over several systems              */
+} npf_batch_report;
+
+/* Host only, synchronous.  problems[count]: as for npf_plan_create (block_modes and
+ * hbm_budget_bytes of each are ignored).  hbm_budget_bytes caps the workspace of a wave
+ * (0 = all systems in one wave).  Errors: NPF_E_INVALID (bad problem, count < 1),
+ * NPF_E_UNSUPPORTED (precision, order or size outside the batched kernels),
+ * NPF_E_BUDGET (one system alone exceeds the budget). */
+int npf_batch_create(const npf_problem *problems, int64_t count, int64_t hbm_budget_bytes,
+                     npf_batch_t *batch_out);
+int npf_batch_info(npf_batch_t batch, npf_batch_report *report);
+void npf_batch_destroy(npf_batch_t batch);
+
+/* Runs every system.  Host arrays of device pointers, one entry per system s:
+ *   A[s*(NPF_MAX_ORDER-1) + M-2]   descriptor of A_M of system s (M = 2..N_s; host array)
+ *   U[s], V[s], lambda[s]          Psi, Phi, eigenvalues as for npf_run
+ *   P_out[s]                       [N_s-1][n][n] complex128 or NULL (P_out may be NULL)
+ *   npf_out[s]                     [n][n] complex128
+ * ws: device workspace of at least workspace_bytes, owned by the call until it completes.
+ * Asynchronous on `stream`; on a non-NULL stream the launch sequence is captured once per
+ * argument set and replayed.  Errors as npf_run. */
+int npf_batch_run(npf_batch_t batch, const npf_tensor *A, const void *const *U,
+                  const void *const *V, const void *const *lambda, void *ws, int64_t ws_bytes,
+                  void *const *P_out, void *const *npf_out, void *stream);
+
+/* Autotuner: times every shared launch for each candidate number of workgroups per
+ * launch (eager runs with events on `stream`, synchronous), keeps the fastest per launch
+ * and returns the chosen counts in chosen[launch] (nullable, shared_launches entries).
+ * The same arguments as npf_batch_run; its outputs are written as by a run. */
+int npf_batch_tune(npf_batch_t batch, const npf_tensor *A, const void *const *U,
+                   const void *const *V, const void *const *lambda, void *ws, int64_t ws_bytes,
+                   void *const *P_out, void *const *npf_out, void *stream, int64_t *chosen);
+
+/* One shared launch of a batch (launches in run order), for measurement. */
+typedef struct npf_batch_launch {
+    int32_t wave;
+    int32_t kind;               /* 0: chain stage `stage` of `order`; 1: fused last stage */
+    int32_t npad;               /* padded size of the systems it runs                    */
+    int32_t order, stage, systems;
+    int64_t workgroups;
+    double flops;               /* algorithmic flops (complex multiply-add = 8)          */
+    double ms;                  /* duration in the last npf_batch_time run (0 before)    */
+} npf_batch_launch;
+
+/* Copies up to `cap` launch records into out (nullable) and their number into *count. */
+int npf_batch_launches(npf_batch_t batch, npf_batch_launch *out, int64_t cap, int64_t *count);
+
+/* One eager run with an event pair around every shared launch (synchronous); the
+ * durations land in the launch records.  Arguments and outputs as npf_batch_run. */
+int npf_batch_time(npf_batch_t batch, const npf_tensor *A, const void *const *U,
+                   const void *const *V, const void *const *lambda, void *ws, int64_t ws_bytes,
+                   void *const *P_out, void *const *npf_out, void *stream);
+
 /* Materialises rows [k0, k1) of a hash-generated derivative tensor (the NPF_SRC_HASH
  * source; the paper's own tensors come from finite differences of the model, for which
  * this generator is the synthetic stand-in): out[(k - k0)*U_M + r] (device, FP64, caller

@@ -26,7 +26,8 @@ EXPORTED = [
     "npf_plan_create", "npf_plan_info", "npf_plan_destroy", "npf_modal_contract",
     "npf_normal_form", "npf_assemble", "npf_finalize", "npf_run", "npf_alg1_batches",
     "npf_plan_profile", "npf_plan_kernel_times", "npf_error_string", "npf_last_error",
-    "npf_hash_fill",
+    "npf_hash_fill", "npf_batch_create", "npf_batch_info", "npf_batch_destroy",
+    "npf_batch_run", "npf_batch_tune", "npf_batch_launches", "npf_batch_time",
 ]
 
 
@@ -73,6 +74,17 @@ class NpfPlanReport(ctypes.Structure):
     ]
 
 
+class NpfBatchLaunch(ctypes.Structure):
+    _fields_ = [("wave", ctypes.c_int32), ("kind", ctypes.c_int32), ("npad", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("stage", ctypes.c_int32), ("systems", ctypes.c_int32),
+                ("workgroups", ctypes.c_int64), ("flops", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+class NpfBatchReport(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("systems", "waves", "workspace_bytes",
+                                               "modal_entries", "launches", "shared_launches")]
+
+
 _lib = None
 
 
@@ -102,13 +114,25 @@ def lib():
         L.npf_plan_kernel_times.argtypes = [P, ctypes.POINTER(NpfKernelTime), i32,
                                             ctypes.POINTER(i32)]
         L.npf_hash_fill.argtypes = [i64, i32, ctypes.c_uint64, dbl, i64, i64, P, P]
+        PP = ctypes.POINTER(P)
+        L.npf_batch_create.argtypes = [ctypes.POINTER(NpfProblem), i64, i64, ctypes.POINTER(P)]
+        L.npf_batch_info.argtypes = [P, ctypes.POINTER(NpfBatchReport)]
+        L.npf_batch_destroy.argtypes = [P]
+        L.npf_batch_destroy.restype = None
+        L.npf_batch_run.argtypes = [P, ctypes.POINTER(NpfTensor), PP, PP, PP, P, i64, PP, PP, P]
+        L.npf_batch_tune.argtypes = [P, ctypes.POINTER(NpfTensor), PP, PP, PP, P, i64, PP, PP, P,
+                                     ctypes.POINTER(i64)]
+        L.npf_batch_time.argtypes = [P, ctypes.POINTER(NpfTensor), PP, PP, PP, P, i64, PP, PP, P]
+        L.npf_batch_launches.argtypes = [P, ctypes.POINTER(NpfBatchLaunch), i64, ctypes.POINTER(i64)]
         L.npf_error_string.argtypes = [ctypes.c_int]
         L.npf_error_string.restype = ctypes.c_char_p
         L.npf_last_error.argtypes = []
         L.npf_last_error.restype = ctypes.c_char_p
         for f in ("npf_plan_create", "npf_plan_info", "npf_modal_contract", "npf_normal_form",
                   "npf_assemble", "npf_finalize", "npf_run", "npf_plan_profile",
-                  "npf_plan_kernel_times", "npf_hash_fill"):
+                  "npf_plan_kernel_times", "npf_hash_fill", "npf_batch_create",
+                  "npf_batch_info", "npf_batch_run", "npf_batch_tune", "npf_batch_launches",
+                  "npf_batch_time"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -331,3 +355,104 @@ def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0
     out = npf.cpu().numpy()
     plan.close()
     return out, Ps
+
+
+# ----------------------------------------------------------------------------- batches
+class Batch:
+    """npf_batch_*: many systems (split-BF16, N <= 4, n <= 256) through the hot path in one
+    call; waves of systems under ``budget_bytes`` of workspace."""
+
+    def __init__(self, systems, budget_bytes: int = 0):
+        count = len(systems)
+        probs = (NpfProblem * count)()
+        for q, sy in enumerate(systems):
+            probs[q] = NpfProblem(sy.n, sy.order_max, PRECISIONS["bf16x3"], sy.eps, sy.tau,
+                                  sy.delta, 0, 0, 0, 0)
+        h = ctypes.c_void_p()
+        _check(lib().npf_batch_create(probs, count, int(budget_bytes), ctypes.byref(h)),
+               "npf_batch_create")
+        self._h = h
+        self.count = count
+        self.orders = [sy.order_max for sy in systems]
+        self.ns = [sy.n for sy in systems]
+        r = NpfBatchReport()
+        _check(lib().npf_batch_info(self._h, ctypes.byref(r)), "npf_batch_info")
+        self.report = {f: int(getattr(r, f)) for f, _ in NpfBatchReport._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().npf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, device):
+        import torch
+        return torch.empty(max(1, self.report["workspace_bytes"]), dtype=torch.uint8, device=device)
+
+    def _arrays(self, dev_systems, P_outs, npf_outs):
+        S = self.count
+        A = (NpfTensor * (S * (NPF_MAX_ORDER - 1)))()
+        for q, d in enumerate(dev_systems):
+            for t in d.tensors:
+                A[q * (NPF_MAX_ORDER - 1) + t.order - 2] = t.desc
+        arr = lambda xs: (ctypes.c_void_p * S)(*[None if x is None else x.data_ptr() for x in xs])
+        U = arr([d.U for d in dev_systems])
+        V = arr([d.V for d in dev_systems])
+        lam = arr([d.lam for d in dev_systems])
+        P = arr(P_outs) if P_outs is not None else None
+        N = arr(npf_outs)
+        return A, U, V, lam, P, N
+
+    def run(self, dev_systems, ws, P_outs, npf_outs, stream=None):
+        A, U, V, lam, P, N = self._arrays(dev_systems, P_outs, npf_outs)
+        _check(lib().npf_batch_run(self._h, A, U, V, lam, _ptr(ws), ws.numel(), P, N,
+                                   _stream(stream)), "npf_batch_run")
+
+    def tune(self, dev_systems, ws, P_outs, npf_outs, stream=None):
+        A, U, V, lam, P, N = self._arrays(dev_systems, P_outs, npf_outs)
+        chosen = (ctypes.c_int64 * max(1, self.report["shared_launches"]))()
+        _check(lib().npf_batch_tune(self._h, A, U, V, lam, _ptr(ws), ws.numel(), P, N,
+                                    _stream(stream), chosen), "npf_batch_tune")
+        return list(chosen)[: self.report["shared_launches"]]
+
+
+    def time_launches(self, dev_systems, ws, P_outs, npf_outs, stream=None):
+        """One eager run with events around every shared launch; returns the launch records
+        (dicts) with their durations."""
+        A, U, V, lam, P, N = self._arrays(dev_systems, P_outs, npf_outs)
+        _check(lib().npf_batch_time(self._h, A, U, V, lam, _ptr(ws), ws.numel(), P, N,
+                                    _stream(stream)), "npf_batch_time")
+        return self.launches()
+
+    def launches(self):
+        cnt = ctypes.c_int64()
+        _check(lib().npf_batch_launches(self._h, None, 0, ctypes.byref(cnt)), "npf_batch_launches")
+        arr = (NpfBatchLaunch * max(1, cnt.value))()
+        _check(lib().npf_batch_launches(self._h, arr, cnt.value, ctypes.byref(cnt)),
+               "npf_batch_launches")
+        return [{f: getattr(arr[i], f) for f, _ in NpfBatchLaunch._fields_} for i in range(cnt.value)]
+
+
+def compute_batch(systems, device="cuda:0", budget_bytes: int = 0, tune: bool = False,
+                  stream=None):
+    """Run a batch of systems; returns [(NPF, {M: P_M})] per system as numpy arrays."""
+    import torch
+    devs = [upload_system(sy, device) for sy in systems]
+    b = Batch(systems, budget_bytes)
+    ws = b.workspace(device)
+    P = [torch.empty((sy.order_max - 1, sy.n, sy.n), dtype=torch.complex128, device=device)
+         for sy in systems]
+    N = [torch.empty((sy.n, sy.n), dtype=torch.complex128, device=device) for sy in systems]
+    if tune:
+        b.tune(devs, ws, P, N, stream)
+    b.run(devs, ws, P, N, stream)
+    torch.cuda.synchronize(device)
+    out = [(N[q].cpu().numpy(), {M: P[q][M - 2].cpu().numpy() for M in range(2, sy.order_max + 1)})
+           for q, sy in enumerate(systems)]
+    b.close()
+    return out

@@ -17,6 +17,9 @@ int check_hip(hipError_t e, const char *where)
     return fail(NPF_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+}  // namespace
+
+namespace npf {
 int check_tensor(const npf_plan_s *p, const npf_tensor *A, int M)
 {
     if (!A) return fail(NPF_E_INVALID, "null tensor descriptor");
@@ -40,6 +43,9 @@ int check_tensor(const npf_plan_s *p, const npf_tensor *A, int M)
     }
     return fail(NPF_E_INVALID, "unknown tensor kind");
 }
+}  // namespace npf
+
+namespace {
 
 int check_order_block(const npf_plan_s *p, int32_t order, int64_t block)
 {

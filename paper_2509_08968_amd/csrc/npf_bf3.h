@@ -16,9 +16,7 @@
 
 namespace npf {
 
-namespace {
-
-constexpr int kThreads = 256;
+constexpr int kBf3Threads = 256;
 
 struct Bf3Args {
     const void *X;           // fused: T_{M-1} [U_{M-1}][n][Jpad]; stage: T_{i-1}
@@ -34,6 +32,26 @@ struct Bf3Args {
     int M, i;
     double eps, tau2;
 };
+
+// Position of a workgroup among the workgroups of its system.
+struct BlockPos {
+    int64_t x, gx;           // index along the items, and their number
+    int y, z;
+    int sys;
+};
+
+// For a launch over several systems: system s owns workgroups [first[s], first[s+1]) of
+// grid.x (every system at least one).
+__device__ __forceinline__ BlockPos system_block(const int32_t *__restrict__ first, int nsys)
+{
+    const int32_t b = int32_t(blockIdx.x);
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    return BlockPos{b - first[lo], first[lo + 1] - first[lo], int(blockIdx.y), int(blockIdx.z), lo};
+}
 
 template <int NP>
 __device__ __forceinline__ void copy_to_lds(char *dst, const void *src, int64_t bytes)
@@ -112,6 +130,19 @@ inline Bf3Args stage_args(const ChainArgs &ca, int i)
     return a;
 }
 
-}  // namespace
+// Arguments of the fused last stage of order M for the block of modes [j0, j0 + J).
+inline Bf3Args fused_args(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
+                          char *ws)
+{
+    Bf3Args a = base_args(p, ws, lam);
+    a.X = ws + p->lay.buf[(M - 1) % 2];
+    a.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
+    a.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
+    a.J = J;
+    a.j0 = j0;
+    a.items = p->U[M - 1];
+    a.M = M;
+    return a;
+}
 
 }  // namespace npf

@@ -5,10 +5,11 @@ namespace npf {
 
 namespace {
 
+constexpr int kThreads = kBf3Threads;
+
 // ------------------------------------------------------------------ fused last stage
 template <int NP, int M>
-__global__ void __launch_bounds__(kThreads)
-fused_bf3(Bf3Args a)
+__device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos bp)
 {
     constexpr int NKT = NP / 16, KC = NP / 32, N2 = NP * NP;
     extern __shared__ __align__(16) char lds[];
@@ -25,7 +26,7 @@ fused_bf3(Bf3Args a)
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
+    const int64_t jw = int64_t(bp.y) * 64 + wave * 16;
     const bool wave_on = jw < a.Jpad;
     const int64_t jl = jw + c;
     const bool j_ok = wave_on && jl < a.J;
@@ -53,14 +54,14 @@ fused_bf3(Bf3Args a)
                 xn[kc][s] = ar < nn ? Xp[ar * jp] : make_float2(0.f, 0.f);
             }
     };
-    int64_t it = blockIdx.x;
+    int64_t it = bp.x;
     uint64_t pk_next = 0;
     if (wave_on && it < a.items) {
         load_x(it);
         pk_next = a.ptab[it];
     }
     if (wave_on)
-    for (; it < a.items; it += gridDim.x) {
+    for (; it < a.items; it += bp.gx) {
         // Split this item's rows, then start loading the next item's into the same registers.
         Split3 xr[KC], xi[KC], xn_[KC];
 #pragma unroll
@@ -69,7 +70,7 @@ fused_bf3(Bf3Args a)
             xn_[kc] = negx3(xi[kc]);
         }
         const uint64_t pk = pk_next;
-        const int64_t itn = it + gridDim.x;
+        const int64_t itn = it + bp.gx;
         if (itn < a.items) {
             load_x(itn);
             pk_next = a.ptab[itn];
@@ -184,7 +185,7 @@ fused_bf3(Bf3Args a)
         }
     }
     if (!wave_on) return;
-    double2 *dst = a.parts + int64_t(blockIdx.x) * a.Jpad * a.n;
+    double2 *dst = a.parts + int64_t(bp.x) * a.Jpad * a.n;
 #pragma unroll
     for (int kt = 0; kt < NKT; ++kt) {
         const int64_t k = kt * 16 + c;
@@ -197,6 +198,23 @@ fused_bf3(Bf3Args a)
     }
 }
 
+template <int NP, int M>
+__global__ void __launch_bounds__(kThreads)
+fused_bf3(Bf3Args a)
+{
+    fused_bf3_body<NP, M>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
+}
+
+// The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
+// run system s with the arguments as[s].
+template <int NP, int M>
+__global__ void __launch_bounds__(kThreads)
+fused_bf3_multi(const Bf3Args *__restrict__ as, const int32_t *__restrict__ first, int nsys)
+{
+    const BlockPos bp = system_block(first, nsys);
+    fused_bf3_body<NP, M>(as[bp.sys], bp);
+}
+
 }  // namespace
 
 bool bf3_small_supported(const npf_plan_s *p)
@@ -207,14 +225,7 @@ bool bf3_small_supported(const npf_plan_s *p)
 hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
                             char *ws, int64_t groups, hipStream_t s)
 {
-    Bf3Args a = base_args(p, ws, lam);
-    a.X = ws + p->lay.buf[(M - 1) % 2];
-    a.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
-    a.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
-    a.J = J;
-    a.j0 = j0;
-    a.items = p->U[M - 1];
-    a.M = M;
+    const Bf3Args a = fused_args(p, M, j0, J, lam, ws);
     const dim3 grid{unsigned(groups), unsigned((p->Jpad + 63) / 64), 1u};
     const size_t shm = size_t(32 * p->npad * p->npad + 16 * p->npad);
 #define NPF_FUSED_CASE(NP_, M_)                                                   \
@@ -231,5 +242,23 @@ hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, c
 
 // Items taken at once by a workgroup of the t-range kernels: four waves of 16 modes share
 // the block's 16-mode tiles, the remaining waves take further items.
+
+hipError_t launch_fused_bf3_multi(int npad, int M, const MultiLaunch &m)
+{
+    const dim3 grid{unsigned(m.groups), unsigned(m.gy), 1u};
+    const size_t shm = size_t(32 * npad * npad + 16 * npad);
+    const Bf3Args *as = static_cast<const Bf3Args *>(m.args);
+#define NPF_FUSED_MULTI(NP_, M_)                                                           \
+    if (npad == NP_ && M == M_) {                                                         \
+        set_lds_limit(fused_bf3_multi<NP_, M_>, int(shm));                                 \
+        hipLaunchKernelGGL((fused_bf3_multi<NP_, M_>), grid, dim3(kThreads), shm, m.stream, \
+                           as, m.first, m.nsys);                                           \
+        return hipGetLastError();                                                          \
+    }
+    NPF_FUSED_MULTI(32, 2) NPF_FUSED_MULTI(32, 3) NPF_FUSED_MULTI(32, 4)
+    NPF_FUSED_MULTI(64, 2) NPF_FUSED_MULTI(64, 3) NPF_FUSED_MULTI(64, 4)
+#undef NPF_FUSED_MULTI
+    return hipErrorInvalidValue;
+}
 
 }  // namespace npf

@@ -5,6 +5,8 @@ namespace npf {
 
 namespace {
 
+constexpr int kThreads = kBf3Threads;
+
 // ------------------------------------------------------------------ fused last stage, n > 64
 // Same arithmetic as fused_bf3; a workgroup owns one 32-wide t-slice (grid.z) of every
 // item: the slices of Phi^T and zeta live in LDS, the reduction runs over the slice's t
@@ -17,8 +19,7 @@ namespace {
 // in KS ranges over grid.y (the first product is recomputed per range) so that the FP64
 // accumulators fit in registers and the zeta slice in LDS.
 template <int NP, int M, int IPW, int KS>
-__global__ void __launch_bounds__(kThreads)
-fused_bf3_tr(Bf3Args a)
+__device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockPos bp)
 {
     constexpr int NKT = NP / 16 / KS, KC = NP / 32, AG = NP / 8, N2 = NP * NP;
     constexpr int KW = NKT * 16;     // states k of this workgroup's range
@@ -29,8 +30,8 @@ fused_bf3_tr(Bf3Args a)
     __bf16 *Lphi = reinterpret_cast<__bf16 *>(lds);
     __bf16 *Lz = reinterpret_cast<__bf16 *>(lds + 12 * PLP);
     double2 *Llam = reinterpret_cast<double2 *>(lds + 12 * PLP + 12 * PLZ);
-    const int slice = int(blockIdx.z), t_base = slice * 32;
-    const int kh = int(blockIdx.y) % KS, jgrp = int(blockIdx.y) / KS;
+    const int slice = int(bp.z), t_base = slice * 32;
+    const int kh = int(bp.y) % KS, jgrp = int(bp.y) / KS;
     const int k_base = kh * KW;
     {
         const int4 *gp = reinterpret_cast<const int4 *>(a.phiE);
@@ -62,7 +63,7 @@ fused_bf3_tr(Bf3Args a)
     const double2 lam_j = j_ok ? Llam[a.j0 + jl] : make_double2(0.0, 0.0);
     const float guard = fmaxf(float(a.tau2), float(4.0 * a.eps * a.eps));
     const int nn = int(a.n), jp = int(a.Jpad);
-    const int64_t istride = int64_t(gridDim.x) * IPW;
+    const int64_t istride = int64_t(bp.gx) * IPW;
 
     double pacc_r[NKT][4], pacc_i[NKT][4];
 #pragma unroll
@@ -83,7 +84,7 @@ fused_bf3_tr(Bf3Args a)
     // The slice has work for an item when some t in it is >= last(p).
     auto active = [&](uint64_t pk) { return t_base + 32 > last_of(pk); };
 
-    int64_t it = int64_t(blockIdx.x) * IPW + islot;
+    int64_t it = int64_t(bp.x) * IPW + islot;
     uint64_t pk = (it < a.items) ? a.ptab[it] : 0;
     float2 cur[8];
     if (wave_on && it < a.items && active(pk)) load_chunk(it, 0, cur);
@@ -220,7 +221,7 @@ fused_bf3_tr(Bf3Args a)
         pk = pkn;
     }
     if (!wave_on) return;
-    double2 *dst = a.parts + ((int64_t(blockIdx.z) * gridDim.x + blockIdx.x) * IPW + islot) *
+    double2 *dst = a.parts + ((int64_t(bp.z) * bp.gx + bp.x) * IPW + islot) *
                                  a.Jpad * a.n;
 #pragma unroll
     for (int kt = 0; kt < NKT; ++kt) {
@@ -232,6 +233,23 @@ fused_bf3_tr(Bf3Args a)
             dst[j * a.n + k] = make_double2(pacc_r[kt][r], pacc_i[kt][r]);
         }
     }
+}
+
+template <int NP, int M, int IPW, int KS>
+__global__ void __launch_bounds__(kThreads)
+fused_bf3_tr(Bf3Args a)
+{
+    fused_bf3_tr_body<NP, M, IPW, KS>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
+}
+
+// The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
+// run system s with the arguments as[s].
+template <int NP, int M, int IPW, int KS>
+__global__ void __launch_bounds__(kThreads)
+fused_bf3_tr_multi(const Bf3Args *__restrict__ as, const int32_t *__restrict__ first, int nsys)
+{
+    const BlockPos bp = system_block(first, nsys);
+    fused_bf3_tr_body<NP, M, IPW, KS>(as[bp.sys], bp);
 }
 
 }  // namespace
@@ -252,17 +270,10 @@ int64_t fused_bf3_tr_slices(const npf_plan_s *p, int64_t Jpad)
 hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J,
                                const double *lam, char *ws, int64_t groups, hipStream_t s)
 {
-    Bf3Args a = base_args(p, ws, lam);
-    a.X = ws + p->lay.buf[(M - 1) % 2];
-    a.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
-    a.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
-    a.J = J;
-    a.j0 = j0;
-    a.items = p->U[M - 1];
-    a.M = M;
+    const Bf3Args a = fused_args(p, M, j0, J, lam, ws);
     const int NP = int(p->npad);
     const int ipw = bf3_items_per_group(p->Jpad);
-    const int ks = NP > 224 ? 4 : (NP > 128 ? 2 : 1);
+    const int ks = fused_bf3_tr_kranges(NP);
     const int64_t jgroups = (p->Jpad / 16 * ipw + 3) / 4;
     const dim3 grid{unsigned(groups), unsigned(jgroups * ks), unsigned(NP / 32)};
     const size_t shm = size_t(12 * NP * 32 + 12 * 32 * (NP / ks) + 16 * NP);
@@ -287,6 +298,31 @@ hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J
 bool bf3_tr_fused_supported(const npf_plan_s *p)
 {
     return p->prec == NPF_BF16X3 && p->npad >= 96 && p->npad <= 256 && p->N <= 4;
+}
+
+// State ranges of the reduction for a system of npad states.
+int fused_bf3_tr_kranges(int64_t npad) { return npad > 224 ? 4 : (npad > 128 ? 2 : 1); }
+
+hipError_t launch_fused_bf3_tr_multi(int npad, int M, const MultiLaunch &m)
+{
+    const int ks = fused_bf3_tr_kranges(npad);
+    const dim3 grid{unsigned(m.groups), unsigned(m.gy * ks), unsigned(npad / 32)};
+    const size_t shm = size_t(12 * npad * 32 + 12 * 32 * (npad / ks) + 16 * npad);
+    const Bf3Args *as = static_cast<const Bf3Args *>(m.args);
+#define NPF_FUSED_TR_MULTI(NP_, M_)                                                          \
+    if (npad == NP_ && M == M_) {                                                           \
+        constexpr int KS_ = NP_ > 224 ? 4 : (NP_ > 128 ? 2 : 1);                             \
+        set_lds_limit(fused_bf3_tr_multi<NP_, M_, 1, KS_>, int(shm));                         \
+        hipLaunchKernelGGL((fused_bf3_tr_multi<NP_, M_, 1, KS_>), grid, dim3(kThreads), shm, \
+                           m.stream, as, m.first, m.nsys);                                   \
+        return hipGetLastError();                                                            \
+    }
+#define NPF_FUSED_TR_MULTI_NP(NP_) NPF_FUSED_TR_MULTI(NP_, 2) NPF_FUSED_TR_MULTI(NP_, 3) NPF_FUSED_TR_MULTI(NP_, 4)
+    NPF_FUSED_TR_MULTI_NP(96) NPF_FUSED_TR_MULTI_NP(128) NPF_FUSED_TR_MULTI_NP(160)
+    NPF_FUSED_TR_MULTI_NP(192) NPF_FUSED_TR_MULTI_NP(224) NPF_FUSED_TR_MULTI_NP(256)
+#undef NPF_FUSED_TR_MULTI_NP
+#undef NPF_FUSED_TR_MULTI
+    return hipErrorInvalidValue;
 }
 
 }  // namespace npf

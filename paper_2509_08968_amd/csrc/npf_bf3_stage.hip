@@ -5,10 +5,11 @@ namespace npf {
 
 namespace {
 
+constexpr int kThreads = kBf3Threads;
+
 // ------------------------------------------------------------------ one chain stage
 template <int NP, int SUF>
-__global__ void __launch_bounds__(kThreads)
-stage_bf3(Bf3Args a)
+__device__ __forceinline__ void stage_bf3_body(const Bf3Args &a, const BlockPos bp)
 {
     constexpr int NTT = NP / 16, KC = NP / 32;
     extern __shared__ __align__(16) char lds[];
@@ -21,7 +22,7 @@ stage_bf3(Bf3Args a)
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
+    const int64_t jw = int64_t(bp.y) * 64 + wave * 16;
     const bool wave_on = jw < a.Jpad;
     const float2 *X = static_cast<const float2 *>(a.X);
 
@@ -62,19 +63,19 @@ stage_bf3(Bf3Args a)
             }
     };
 
-    int64_t it = blockIdx.x;
+    int64_t it = bp.x;
     int buf = 0;
     if (it < a.items) build_idx(it, 0);
     __syncthreads();          // also orders the LDS copy of Phi
     if (it < a.items && wave_on) gather_x(it, 0);
-    for (; it < a.items; it += gridDim.x, buf ^= 1) {
+    for (; it < a.items; it += bp.gx, buf ^= 1) {
         Split3 xr[KC], xi[KC], xn_[KC];
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
             split_x(xn[kc], xr[kc], xi[kc]);
             xn_[kc] = negx3(xi[kc]);
         }
-        const int64_t itn = it + gridDim.x;
+        const int64_t itn = it + bp.gx;
         if (itn < a.items) build_idx(itn, buf ^ 1);
         __syncthreads();
         if (itn < a.items && wave_on) gather_x(itn, buf ^ 1);
@@ -117,6 +118,23 @@ stage_bf3(Bf3Args a)
     }
 }
 
+template <int NP, int SUF>
+__global__ void __launch_bounds__(kThreads)
+stage_bf3(Bf3Args a)
+{
+    stage_bf3_body<NP, SUF>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
+}
+
+// The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
+// run system s with the arguments as[s].
+template <int NP, int SUF>
+__global__ void __launch_bounds__(kThreads)
+stage_bf3_multi(const Bf3Args *__restrict__ as, const int32_t *__restrict__ first, int nsys)
+{
+    const BlockPos bp = system_block(first, nsys);
+    stage_bf3_body<NP, SUF>(as[bp.sys], bp);
+}
+
 }  // namespace
 
 hipError_t launch_stage_bf3_small(const ChainArgs &ca, int i)
@@ -145,6 +163,24 @@ hipError_t launch_stage_bf3_small(const ChainArgs &ca, int i)
 bool bf3_stage_supported(const npf_plan_s *p)
 {
     return p->prec == NPF_BF16X3 && p->N <= 4;
+}
+
+hipError_t launch_stage_bf3_multi(int npad, int suf, const MultiLaunch &m)
+{
+    const dim3 grid{unsigned(m.groups), unsigned(m.gy), 1u};
+    const size_t shm = size_t(12 * npad * npad);
+    const Bf3Args *as = static_cast<const Bf3Args *>(m.args);
+#define NPF_STAGE_MULTI(NP_, S_)                                                           \
+    if (npad == NP_ && suf == S_) {                                                       \
+        set_lds_limit(stage_bf3_multi<NP_, S_>, int(shm));                                 \
+        hipLaunchKernelGGL((stage_bf3_multi<NP_, S_>), grid, dim3(kThreads), shm, m.stream, \
+                           as, m.first, m.nsys);                                           \
+        return hipGetLastError();                                                          \
+    }
+    NPF_STAGE_MULTI(32, 1) NPF_STAGE_MULTI(32, 2) NPF_STAGE_MULTI(32, 3)
+    NPF_STAGE_MULTI(64, 1) NPF_STAGE_MULTI(64, 2) NPF_STAGE_MULTI(64, 3)
+#undef NPF_STAGE_MULTI
+    return hipErrorInvalidValue;
 }
 
 }  // namespace npf

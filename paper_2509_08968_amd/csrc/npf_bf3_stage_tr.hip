@@ -5,6 +5,8 @@ namespace npf {
 
 namespace {
 
+constexpr int kThreads = kBf3Threads;
+
 // ------------------------------------------------------------------ one chain stage, n > 64
 // Same arithmetic as stage_bf3; a workgroup owns a range of TT t-tiles (grid.z) and keeps
 // only that slice of the Phi^T planes in LDS.  The gathered rows are loaded one K-chunk
@@ -12,8 +14,7 @@ namespace {
 // fewer than four 16-mode tiles in the block, the four waves take IPW items per iteration
 // (item slot = wave / (4 / IPW)).
 template <int NP, int SUF, int TT, int IPW>
-__global__ void __launch_bounds__(kThreads)
-stage_bf3_tr(Bf3Args a)
+__device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockPos bp)
 {
     constexpr int KC = NP / 32, TW = TT * 16, AG = NP / 8;
     constexpr int WPI = 4 / IPW;
@@ -23,7 +24,7 @@ stage_bf3_tr(Bf3Args a)
     // iteration's barrier, i.e. after every wave has passed the barrier of iteration k+1.
     __shared__ int32_t sidx[3][IPW][NP];
     __shared__ int64_t rowoff[TW];
-    const int t_base = int(blockIdx.z) * TW;
+    const int t_base = int(bp.z) * TW;
     {
         // Slice [t_base, t_base + TW) of the six planes [pl][a/8][t][a%8].
         const int4 *gsrc = reinterpret_cast<const int4 *>(a.phiE);
@@ -42,12 +43,12 @@ stage_bf3_tr(Bf3Args a)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, c = lane & 15;
     const int islot = wave / WPI;
-    const int64_t jw = (int64_t(blockIdx.y) * WPI + wave % WPI) * 16;
+    const int64_t jw = (int64_t(bp.y) * WPI + wave % WPI) * 16;
     const bool wave_on = jw < a.Jpad && islot < IPW;
     const float2 *X = static_cast<const float2 *>(a.X);
     const unsigned jp = unsigned(a.Jpad);
     const int nn = int(a.n);
-    const int64_t istride = int64_t(gridDim.x) * IPW;
+    const int64_t istride = int64_t(bp.gx) * IPW;
 
     // Gather tables of the items ib .. ib + IPW - 1 into buffer buf.
     auto build_idx = [&](int64_t ib, int buf) {
@@ -88,7 +89,7 @@ stage_bf3_tr(Bf3Args a)
     };
 
     // ib: the workgroup's first item of the iteration (uniform); it = ib + islot.
-    int64_t ib = int64_t(blockIdx.x) * IPW;
+    int64_t ib = int64_t(bp.x) * IPW;
     int buf = 0;
     float2 cur[8];
     if (ib < a.items) build_idx(ib, 0);
@@ -163,6 +164,23 @@ stage_bf3_tr(Bf3Args a)
     }
 }
 
+template <int NP, int SUF, int TT, int IPW>
+__global__ void __launch_bounds__(kThreads)
+stage_bf3_tr(Bf3Args a)
+{
+    stage_bf3_tr_body<NP, SUF, TT, IPW>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
+}
+
+// The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
+// run system s with the arguments as[s].
+template <int NP, int SUF, int TT, int IPW>
+__global__ void __launch_bounds__(kThreads)
+stage_bf3_tr_multi(const Bf3Args *__restrict__ as, const int32_t *__restrict__ first, int nsys)
+{
+    const BlockPos bp = system_block(first, nsys);
+    stage_bf3_tr_body<NP, SUF, TT, IPW>(as[bp.sys], bp);
+}
+
 }  // namespace
 
 hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
@@ -193,6 +211,31 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     NPF_STAGE_TR_NP(192, 2) NPF_STAGE_TR_NP(224, 2) NPF_STAGE_TR_NP(256, 2)
 #undef NPF_STAGE_TR_NP
 #undef NPF_STAGE_TR
+    return hipErrorInvalidValue;
+}
+
+// t-tiles per workgroup of the t-range stage kernel for a system of npad states.
+int stage_bf3_tr_tiles(int64_t npad) { return npad == 96 ? 3 : (npad == 128 ? 4 : 2); }
+
+hipError_t launch_stage_bf3_tr_multi(int npad, int suf, const MultiLaunch &m)
+{
+    const int tt = stage_bf3_tr_tiles(npad);
+    const dim3 grid{unsigned(m.groups), unsigned(m.gy), unsigned((npad / 16 + tt - 1) / tt)};
+    const size_t shm = size_t(12 * npad * tt * 16);
+    const Bf3Args *as = static_cast<const Bf3Args *>(m.args);
+#define NPF_STAGE_TR_MULTI(NP_, S_, TT_)                                                       \
+    if (npad == NP_ && suf == S_) {                                                           \
+        set_lds_limit(stage_bf3_tr_multi<NP_, S_, TT_, 1>, int(shm));                          \
+        hipLaunchKernelGGL((stage_bf3_tr_multi<NP_, S_, TT_, 1>), grid, dim3(kThreads), shm,   \
+                           m.stream, as, m.first, m.nsys);                                     \
+        return hipGetLastError();                                                              \
+    }
+#define NPF_STAGE_TR_MULTI_NP(NP_, TT_) \
+    NPF_STAGE_TR_MULTI(NP_, 1, TT_) NPF_STAGE_TR_MULTI(NP_, 2, TT_) NPF_STAGE_TR_MULTI(NP_, 3, TT_)
+    NPF_STAGE_TR_MULTI_NP(96, 3) NPF_STAGE_TR_MULTI_NP(128, 4) NPF_STAGE_TR_MULTI_NP(160, 2)
+    NPF_STAGE_TR_MULTI_NP(192, 2) NPF_STAGE_TR_MULTI_NP(224, 2) NPF_STAGE_TR_MULTI_NP(256, 2)
+#undef NPF_STAGE_TR_MULTI_NP
+#undef NPF_STAGE_TR_MULTI
     return hipErrorInvalidValue;
 }
 

@@ -555,10 +555,18 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
     }
 }
 
+// Workgroups along the items of the fused kernel of order M for the plan's block.
+int64_t fused_default_groups(const npf_plan_s *p, int M) { return fused_gx(p, p->U[M - 1], p->Jpad); }
+
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
                                double *psum, bool first, char *ws, hipStream_t s)
 {
-    const int64_t nparts = fused_groups(p, M);
+    return launch_reduce_parts_n(p, fused_groups(p, M), j0, J, P, psum, first, ws, s);
+}
+
+hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
+                                 double *P, double *psum, bool first, char *ws, hipStream_t s)
+{
     const int64_t nrun = (nparts + kRun - 1) / kRun;
     const int64_t per = J * p->n;
     auto blocks = [](int64_t work) {

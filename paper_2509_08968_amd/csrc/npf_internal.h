@@ -9,11 +9,17 @@
 
 #include "npf.h"
 
+struct npf_plan_s;
+
 namespace npf {
 
 // Per-thread error message for npf_last_error().
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
+
+// Checks a derivative-tensor descriptor of order M against a plan (NPF_OK or an error code
+// with the message set).
+int check_tensor(const npf_plan_s *p, const npf_tensor *A, int M);
 
 // binom(a, b) on the host (exact; 0 outside 0 <= b <= a).
 int64_t binom(int64_t a, int64_t b);
@@ -142,6 +148,27 @@ hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, c
                             char *ws, int64_t groups, hipStream_t s);
 hipError_t launch_stage_bf3(const ChainArgs &a, int i);
 hipError_t launch_stage_bf3_small(const ChainArgs &a, int i);
+
+// One launch over several systems of the same padded size: system s runs on workgroups
+// [first[s], first[s+1]) of grid.x (at least one each) with the kernel arguments args[s].
+struct MultiLaunch {
+    const void *args;         // device: kernel argument records [nsys]
+    const int32_t *first;     // device: [nsys + 1]
+    int nsys;
+    int64_t groups;           // first[nsys]
+    int gy;                   // 64-mode groups of the largest block
+    hipStream_t stream;
+};
+hipError_t launch_fused_bf3_multi(int npad, int M, const MultiLaunch &m);
+hipError_t launch_fused_bf3_tr_multi(int npad, int M, const MultiLaunch &m);
+hipError_t launch_stage_bf3_multi(int npad, int suf, const MultiLaunch &m);
+hipError_t launch_stage_bf3_tr_multi(int npad, int suf, const MultiLaunch &m);
+int fused_bf3_tr_kranges(int64_t npad);
+int stage_bf3_tr_tiles(int64_t npad);
+// Partial sums of a block's fused-kernel slots (nparts of them) into P rows and psum.
+hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
+                                 double *P, double *psum, bool first, char *ws, hipStream_t s);
+int64_t fused_default_groups(const npf_plan_s *p, int M);
 bool bf3_tr_fused_supported(const npf_plan_s *p);
 int bf3_items_per_group(int64_t Jpad);
 int64_t fused_bf3_tr_slices(const npf_plan_s *p, int64_t Jpad);
