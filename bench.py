@@ -104,6 +104,15 @@ def kernel_work(name, sysm, plan):
             nnz = int(t.desc.nnz)
             return 4.0 * nnz * J, 8.0 * nnz + 8.0 * J * U[M], "alu", False
         return 4.0 * n * J * U[M], 8.0 * n * U[M], "alu", False
+    if what == "tucker_support":
+        return 0.0, 0.0, "alu", False
+    if what == "tucker_w":
+        # W: about s^M complex multiply-adds per (p, k), s = support bound
+        sm = sysm_support(sysm)
+        return (8.0 * sm ** M * U[M - 1] * n, 16.0 * U[M - 1] * n * sm, "alu", False)
+    if what == "tucker_psi":
+        sm = sysm_support(sysm)
+        return (8.0 * U[M - 1] * n * J * sm, 8.0 * U[M - 1] * n * J, "hbm", False)
     if what.startswith("stage"):
         i = int(what[5:])
         return (8.0 * J * n * U[i] * U[M - i], 8.0 * J * (U[i - 1] * U[M - i + 1] + U[i] * U[M - i]),
@@ -119,6 +128,10 @@ def kernel_work(name, sysm, plan):
     return 0.0, 0.0, "alu", False
 
 
+def sysm_support(sysm):
+    return getattr(sysm, "support_max", 0) or 8
+
+
 def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0):
     """Time `steps` steps on a dedicated stream (graph replay after the first call), then,
     if `profile`, run the same steps eagerly with HIP events around every kernel launch."""
@@ -128,7 +141,8 @@ def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0):
     n, N = s.n, s.order_max
     P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
     npf = torch.empty((n, n), dtype=torch.complex128, device=device)
-    mk = lambda: B.Plan(n, N, precision, s.eps, s.tau, s.delta, budget_bytes=budget)
+    mk = lambda: B.Plan(n, N, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
+                        support_max=s.support_max)
     plan0 = mk()
     ws = plan0.workspace(device)
     stream = torch.cuda.Stream(device=device)       # default priority
@@ -292,13 +306,15 @@ def bench_batch(args):
     # Per-system rates: each system alone through npf_run (graph replay), same precision.
     solo = None
     if not args.no_solo:
-        big = max(B.Plan(s.n, s.order_max, "bf16x3").workspace_bytes for s in ss)
+        big = max(B.Plan(s.n, s.order_max, "bf16x3", support_max=s.support_max).workspace_bytes
+                  for s in ss)
         del ws
         torch.cuda.empty_cache()
         wsolo = torch.empty(big, dtype=torch.uint8, device=device)
         rates, total = [], 0.0
         for q, s in enumerate(ss):
-            plan = B.Plan(s.n, s.order_max, "bf16x3", s.eps, s.tau, s.delta)
+            plan = B.Plan(s.n, s.order_max, "bf16x3", s.eps, s.tau, s.delta,
+                          support_max=s.support_max)
             plan.run(devs[q].tensors, devs[q].U, devs[q].V, devs[q].lam, wsolo, P[q], N[q], st)
             a, c = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(st)

@@ -91,7 +91,12 @@ typedef struct npf_problem {
     int64_t hbm_budget_bytes;  /* workspace cap, the M_limit of Alg. 1; 0 = none      */
     int64_t block_modes;       /* output modes per block; 0 = chosen by the planner   */
     int32_t flags;             /* NPF_FLAG_* bits                                      */
-    int32_t reserved;
+    int32_t support_max;       /* 1..8: no row k of a sparse A_M involves more than this
+                                  many distinct states; order 3 (for n > 64, or any n
+                                  in FP64) and order 2 (for n > 96) then contract each
+                                  row's lower indices over its own states first and apply
+                                  Psi after (a row with more states makes the results
+                                  NaN).  0: no bound, the upper index first everywhere.   */
 } npf_problem;
 
 /* npf_run replays a HIP graph of its launch sequence when called again with the same

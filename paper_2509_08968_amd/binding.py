@@ -57,7 +57,7 @@ class NpfProblem(ctypes.Structure):
         ("n", ctypes.c_int64), ("order_max", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("eps", ctypes.c_double), ("tau", ctypes.c_double), ("delta", ctypes.c_double),
         ("hbm_budget_bytes", ctypes.c_int64), ("block_modes", ctypes.c_int64),
-        ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("support_max", ctypes.c_int32),
     ]
 
 
@@ -172,9 +172,9 @@ class Plan:
 
     def __init__(self, n: int, order_max: int, precision: str = "fp64", eps: float = 1e-9,
                  tau: float = 1e-2, delta: float = 1.0, budget_bytes: int = 0,
-                 block_modes: int = 0, graph: bool = True):
+                 block_modes: int = 0, graph: bool = True, support_max: int = 0):
         prob = NpfProblem(n, order_max, PRECISIONS[precision], eps, tau, delta, budget_bytes,
-                          block_modes, 0 if graph else NPF_FLAG_NO_GRAPH, 0)
+                          block_modes, 0 if graph else NPF_FLAG_NO_GRAPH, int(support_max))
         h = ctypes.c_void_p()
         _check(lib().npf_plan_create(ctypes.byref(prob), ctypes.byref(h)), "npf_plan_create")
         self._h = h
@@ -309,6 +309,7 @@ class DeviceSystem:
     V: object
     tensors: List[DeviceTensor]
     orders: List[int]
+    support_max: int = 0
 
 
 def upload_system(sys, device, sparse: Optional[bool] = None,
@@ -334,17 +335,21 @@ def upload_system(sys, device, sparse: Optional[bool] = None,
         sp = sparse if sparse is not None else (sys.support.get(M) is not None)
         tens.append(upload_tensor(A, M, device, sparse=sp, support=sys.support.get(M)))
     return DeviceSystem(sys.n, c128(sys.lam), c128(sys.U), c128(sys.V), tens,
-                        list(range(2, sys.order_max + 1)))
+                        list(range(2, sys.order_max + 1)), sys.support_max)
 
 
 def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0,
             block_modes: int = 0, sparse: Optional[bool] = None, graph: bool = True,
-            hash_source: bool = True):
-    """Run the fused hot path on one system; returns (NPF, {M: P_M}) as numpy arrays."""
+            hash_source: bool = True, support_max: Optional[int] = None):
+    """Run the fused hot path on one system; returns (NPF, {M: P_M}) as numpy arrays.
+    support_max (default: the system's own bound, 0 when its tensors are not sent sparse)
+    selects the lower-indices-first route for sparse orders."""
     import torch
     dev = upload_system(sys, device, sparse, hash_source)
+    if support_max is None:
+        support_max = sys.support_max if sparse in (None, True) else 0
     plan = Plan(sys.n, sys.order_max, precision, sys.eps, sys.tau, sys.delta, budget_bytes,
-                block_modes, graph)
+                block_modes, graph, support_max)
     ws = plan.workspace(device)
     n, N = sys.n, sys.order_max
     P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
@@ -367,7 +372,7 @@ class Batch:
         probs = (NpfProblem * count)()
         for q, sy in enumerate(systems):
             probs[q] = NpfProblem(sy.n, sy.order_max, PRECISIONS["bf16x3"], sy.eps, sy.tau,
-                                  sy.delta, 0, 0, 0, 0)
+                                  sy.delta, 0, 0, 0, int(sy.support_max))
         h = ctypes.c_void_p()
         _check(lib().npf_batch_create(probs, count, int(budget_bytes), ctypes.byref(h)),
                "npf_batch_create")

@@ -29,16 +29,25 @@ def launch_names(workload: str, precision: str, budget: int = 0):
     from . import binding as B
     from . import inputs as I
     s = I.WORKLOADS[workload]()
-    plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget)
+    plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
+                  support_max=s.support_max)
     names = ["prepare"]
     for M in range(2, s.order_max + 1):
         sparse = s.support.get(M) is not None and M not in s.hashed
+        tucker = sparse and 1 <= s.support_max <= 8 and (
+            (M == 3 and (s.n > 64 or precision == "fp64")) or (M == 2 and s.n > 96))
+        if tucker:
+            names += [f"o{M}_tucker_support.rows", f"o{M}_tucker_support.inverse"]
+            names += ([f"o{M}_tucker_w.y", f"o{M}_tucker_w"] if M == 3 else [f"o{M}_tucker_w"])
         for _ in range(plan.n_blocks):
-            if sparse:
+            if tucker:
+                names.append(f"o{M}_tucker_psi")
+            elif sparse:
                 names += [f"o{M}_psi_a.clear", f"o{M}_psi_a"]
             else:
                 names.append(f"o{M}_psi_a")
-            names += [f"o{M}_stage{i}" for i in range(1, M)]
+            if not tucker:
+                names += [f"o{M}_stage{i}" for i in range(1, M)]
             names += [f"o{M}_fused", f"o{M}_reduce.l1", f"o{M}_reduce.l2"]
     names.append("finalize")
     plan.close()

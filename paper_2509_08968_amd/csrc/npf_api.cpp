@@ -80,9 +80,32 @@ std::string kname(int M, const char *what, int i = -1)
     return s;
 }
 
-int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tensor *A,
-              const void *U, const void *V, void *ws, hipStream_t s)
+// Per-row tables of the lower-indices-first route (once per order).
+int run_rows(const npf_plan_s *p, int M, const npf_tensor *A, const void *V, void *ws, hipStream_t s)
 {
+    int rc;
+    {
+        Timed t(p, kname(M, "tucker_support"), s);
+        rc = check_hip(launch_tucker_support(p, M, A, static_cast<char *>(ws), s),
+                       "per-row support tables");
+    }
+    if (rc) return rc;
+    Timed t(p, kname(M, "tucker_w"), s);
+    return check_hip(launch_tucker_w(p, M, static_cast<const double *>(V), static_cast<char *>(ws), s),
+                     "per-row lower-index contraction");
+}
+
+// T_{M-1} of the block [j0, j0 + J) in buffer (M-1) % 2: the upper-index contraction and
+// the chain stages, or Psi applied to the per-row tables (tucker: run_rows done).
+int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tensor *A,
+              const void *U, const void *V, void *ws, hipStream_t s, bool tucker = false)
+{
+    if (tucker) {
+        Timed t(p, kname(M, "tucker_psi"), s);
+        return check_hip(launch_tucker_psi(p, M, j0, J, static_cast<const double *>(U),
+                                           static_cast<char *>(ws), s),
+                         "upper-index contraction of the per-row tables");
+    }
     ChainArgs a{p, M, j0, J, A, static_cast<const double *>(U), static_cast<const double *>(V),
                 static_cast<char *>(ws), s};
     int rc;
@@ -122,10 +145,12 @@ extern "C" int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block,
     int64_t b0, b1;
     block_range(plan, block, b0, b1);
     rc = stage_operands(plan, U, V, ws, s);
+    const bool tucker = tucker_supported(plan, A, order);
+    if (!rc && tucker) rc = run_rows(plan, order, A, V, ws, s);
     for (int64_t b = b0; b < b1 && rc == NPF_OK; ++b) {
         int64_t j0, J;
         block_modes(plan, b, j0, J);
-        rc = run_chain(plan, order, j0, J, A, U, V, ws, s);
+        rc = run_chain(plan, order, j0, J, A, U, V, ws, s, tucker);
         if (rc) break;
         double *dst = static_cast<double *>(C_out) + 2 * (j0 - b0 * plan->J) * plan->U[order];
         ChainArgs a{plan, order, j0, J, A, static_cast<const double *>(U),
@@ -301,10 +326,12 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
     rc = stage_operands(plan, U, V, ws, s);
     for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
         double *PM = P_out ? static_cast<double *>(P_out) + 2 * (M - 2) * nn : pm;
+        const bool tucker = tucker_supported(plan, &A[M - 2], M);
+        if (tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, s);
         for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
             int64_t j0, J;
             block_modes(plan, b, j0, J);
-            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, s);
+            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, s, tucker);
             if (rc) break;
             {
                 Timed t(plan, kname(M, "fused"), s);

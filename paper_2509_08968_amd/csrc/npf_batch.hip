@@ -53,6 +53,9 @@ struct GraphEntry {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Orders that take the lower-indices-first route (sparse tensors with a support bound).
+bool planned_tucker(const npf_plan_s *p, int M) { return tucker_route(p, M); }
+
 }  // namespace
 
 struct npf_batch_s {
@@ -158,8 +161,20 @@ int run_waves(npf_batch_s *b, const npf_tensor *A, const void *const *U, const v
             for (int s : ws_sys) {
                 const npf_plan_s *p = b->sys[s].plan;
                 if (p->N < M) continue;
-                const ChainArgs ca{p, M, 0, p->n, &A[s * (NPF_MAX_ORDER - 1) + M - 2],
-                                   static_cast<const double *>(U[s]),
+                const npf_tensor *At = &A[s * (NPF_MAX_ORDER - 1) + M - 2];
+                if (planned_tucker(p, M)) {
+                    rc = check_hip(launch_tucker_rows(p, M, At, static_cast<const double *>(V[s]),
+                                                      region(s), st),
+                                   "per-row lower-index contraction");
+                    if (!rc)
+                        rc = check_hip(launch_tucker_psi(p, M, 0, p->n,
+                                                         static_cast<const double *>(U[s]),
+                                                         region(s), st),
+                                       "upper-index contraction of the per-row tables");
+                    if (rc) return rc;
+                    continue;
+                }
+                const ChainArgs ca{p, M, 0, p->n, At, static_cast<const double *>(U[s]),
                                    static_cast<const double *>(V[s]), region(s), st};
                 if ((rc = check_hip(launch_psi_a(ca), "upper-index contraction"))) return rc;
             }
@@ -246,8 +261,11 @@ int check_args(const npf_batch_s *b, const npf_tensor *A, const void *const *U,
         const npf_plan_s *p = b->sys[s].plan;
         if (!U[s] || !V[s] || !lam[s]) return fail(NPF_E_INVALID, "null per-system pointer");
         for (int M = 2; M <= p->N; ++M) {
-            const int rc = check_tensor(p, &A[s * (NPF_MAX_ORDER - 1) + M - 2], M);
+            const npf_tensor *At = &A[s * (NPF_MAX_ORDER - 1) + M - 2];
+            const int rc = check_tensor(p, At, M);
             if (rc) return rc;
+            if (planned_tucker(p, M) && At->kind != NPF_SRC_SPARSE)
+                return fail(NPF_E_INVALID, "a system with a support bound needs sparse tensors");
         }
     }
     (void)npf_out;
@@ -332,6 +350,7 @@ extern "C" int npf_batch_create(const npf_problem *problems, int64_t count, int6
                     for (int s : b->waves[w]) {
                         const npf_plan_s *p = b->sys[s].plan;
                         if (p->npad != npad || p->N < M) continue;
+                        if (L.kind == 0 && planned_tucker(p, M)) continue;
                         L.sys.push_back(s);
                         L.gy = std::max<int>(L.gy, int((p->Jpad + 63) / 64));
                         const double Jn = double(p->Jpad) * double(p->n);
@@ -364,7 +383,7 @@ extern "C" int npf_batch_create(const npf_problem *problems, int64_t count, int6
     // Launches per run: per system prepare, finalize and per order its upper-index
     // contraction (two for sparse sources) and two partial-sum launches; plus the shared.
     int64_t per = 0;
-    for (const Sys &s : b->sys) per += 2 + 4 * (s.plan->N - 1);
+    for (const Sys &s : b->sys) per += 2 + 4 * (s.plan->N - 1);   // Tucker orders: 2 + 2 as well
     b->launches = per + int64_t(b->shared.size()) + 1;
     *batch_out = b;
     return NPF_OK;

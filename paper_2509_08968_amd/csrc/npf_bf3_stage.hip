@@ -118,8 +118,9 @@ __device__ __forceinline__ void stage_bf3_body(const Bf3Args &a, const BlockPos 
     }
 }
 
+// Two workgroups per CU: the register budget is held to 256 per lane.
 template <int NP, int SUF>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, 2)
 stage_bf3(Bf3Args a)
 {
     stage_bf3_body<NP, SUF>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
@@ -128,7 +129,7 @@ stage_bf3(Bf3Args a)
 // The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
 // run system s with the arguments as[s].
 template <int NP, int SUF>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, 2)
 stage_bf3_multi(const Bf3Args *__restrict__ as, const int32_t *__restrict__ first, int nsys)
 {
     const BlockPos bp = system_block(first, nsys);

@@ -72,10 +72,10 @@ __host__ __device__ __forceinline__ void colex_unrank(int64_t r, int m, int64_t 
         int64_t lo = 0, hi = n - 1;  // largest x with colex_term(x, i) <= r
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) / 2;
-            if (colex_term(mid, i) <= r) lo = mid; else hi = mid - 1;
+            if (colex_term_c(mid, i) <= r) lo = mid; else hi = mid - 1;
         }
         t[i - 1] = int32_t(lo);
-        r -= colex_term(lo, i);
+        r -= colex_term_c(lo, i);
     }
 }
 

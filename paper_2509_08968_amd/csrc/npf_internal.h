@@ -33,6 +33,14 @@ struct TupleTables {
     int maxlen = 0;
 };
 
+// Largest per-row support of the lower-indices-first route for sparse tensors.
+constexpr int kTuckerMaxSupport = 8;
+
+// Workspace of that route (offsets in bytes; all zero when the plan has no support bound).
+struct TuckerLayout {
+    int64_t over = 0, S = 0, cnt = 0, inv = 0, invcnt = 0, D = 0, Y = 0, W = 0;
+};
+
 // Workspace layout of a plan.  All offsets are in bytes from the start of `ws` and are
 // multiples of 256.
 struct Layout {
@@ -47,6 +55,7 @@ struct Layout {
     int64_t parts_bytes = 0;
     int64_t parts2 = 0;          // first-level sums of the partials
     int64_t parts2_bytes = 0;
+    TuckerLayout tk;
     int64_t total = 0;
 };
 
@@ -109,6 +118,18 @@ struct ChainArgs {
     char *ws;
     hipStream_t stream;
 };
+
+// Lower indices first for a sparse A_M whose rows involve at most support_max states:
+// per-row support lists and tables, and W (once per order); then T_{M-1} for a block.
+bool tucker_route(const npf_plan_s *p, int M);              // the plan takes the route for order M
+bool tucker_supported(const npf_plan_s *p, const npf_tensor *A, int M);
+hipError_t launch_tucker_rows(const npf_plan_s *p, int M, const npf_tensor *A, const double *V,
+                              char *ws, hipStream_t s);
+hipError_t launch_tucker_support(const npf_plan_s *p, int M, const npf_tensor *A, char *ws,
+                                 hipStream_t s);
+hipError_t launch_tucker_w(const npf_plan_s *p, int M, const double *V, char *ws, hipStream_t s);
+hipError_t launch_tucker_psi(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *U,
+                             char *ws, hipStream_t s);
 
 // G = Psi[j0:j0+J, :] A_M over sorted tuples, into buffer 0 (T_0).
 hipError_t launch_psi_a(const ChainArgs &a);

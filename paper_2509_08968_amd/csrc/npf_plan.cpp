@@ -60,6 +60,18 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     L.parts = take(L.parts_bytes);
     L.parts2_bytes = ((nparts + 15) / 16) * Jpad * p.n * 16;
     L.parts2 = take(L.parts2_bytes);
+    const int smax = p.prob.support_max;
+    if (smax >= 1 && smax <= kTuckerMaxSupport && p.N >= 2) {
+        const int Mt = std::min(p.N, 3);          // the route serves orders 2 and 3
+        L.tk.over = take(p.n * 4);
+        L.tk.S = take(p.n * smax * 4);
+        L.tk.cnt = take(p.n * 4);
+        L.tk.inv = take(p.n * p.n * 4);
+        L.tk.invcnt = take(p.n * 4);
+        L.tk.D = take(p.n * binom(smax + Mt - 1, Mt) * 8);
+        if (Mt == 3) L.tk.Y = take(p.n * smax * p.n * smax * 16);
+        L.tk.W = take(p.U[Mt - 1] * p.n * smax * 16);
+    }
     L.total = off;
     return L;
 }
@@ -83,6 +95,7 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
     if (!std::isfinite(q.delta)) return fail(NPF_E_INVALID, "delta must be finite");
     if (q.hbm_budget_bytes < 0 || q.block_modes < 0)
         return fail(NPF_E_INVALID, "negative budget or block size");
+    if (q.support_max < 0) return fail(NPF_E_INVALID, "negative support bound");
     if (q.n > 256) return fail(NPF_E_UNSUPPORTED, "n > 256 is not supported by the MFMA kernels");
 
     npf_plan_s *p = new (std::nothrow) npf_plan_s();

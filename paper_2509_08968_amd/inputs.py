@@ -70,6 +70,7 @@ class System:
     A     {M: float64 [n, binom(n+M-1, M)]}  packed derivative tensors, M >= 2
     support {M: int64 [s]}      sorted union of ranks that may be nonzero (None = dense)
     hashed  {M: (seed, scale)}  orders whose A_M is hash-generated (A[M] is None)
+    support_max                 most distinct states in one row k of a sparse A_M (0: dense)
     """
 
     name: str
@@ -84,6 +85,7 @@ class System:
     tau: float = 1e-2
     delta: float = 1.0
     hashed: Dict[int, Tuple[int, float]] = dataclasses.field(default_factory=dict)
+    support_max: int = 0        # most distinct states one row k of a sparse A_M involves
 
     @property
     def orders(self) -> List[int]:
@@ -189,7 +191,8 @@ def block_sparse_system(n: int, orders, seed: int, name: str = "block-sparse", *
     for M in orders:
         if M >= 2:
             A[M], S[M] = block_sparse_tensor(n, M, rng)
-    return _finish(name, n, lam, V, A, S, **kw)
+    smax = max(len(x) for x in block_sets(n))
+    return _finish(name, n, lam, V, A, S, support_max=smax, **kw)
 
 
 def resonant_system(n: int, orders, seed: int, n_res2: int = 4, n_res3: int = 4,

@@ -19,18 +19,23 @@ def test_entries_and_single_wave():
     r = b.report
     assert r["systems"] == len(ss) and r["waves"] == 1
     assert r["modal_entries"] == sum(s.n * math.comb(s.n + M - 1, M) for s in ss for M in s.orders)
-    # one shared launch per (padded size, order, stage or fused) present in the batch
-    pads = {}
+    # one shared fused launch per (padded size, order); chain stages only for systems that
+    # do not take the lower-indices-first route (sparse with a support bound, orders <= 3)
+    want = set()
     for s in ss:
         np_ = (s.n + 31) // 32 * 32
-        pads[np_] = max(pads.get(np_, 0), s.order_max)
-    assert r["shared_launches"] == sum(sum(M for M in range(2, N + 1)) for N in pads.values())
+        for M in s.orders:
+            want.add((np_, M, M))
+            if not (s.support_max and ((M == 3 and s.n > 64) or (M == 2 and s.n > 96))):
+                want.update((np_, M, i) for i in range(1, M))
+    assert r["shared_launches"] == len(want)
 
 
 def test_budget_makes_waves():
     ss = systems()
     one = B.Batch(ss).report
-    biggest = max(B.Plan(s.n, s.order_max, "bf16x3").workspace_bytes for s in ss)
+    biggest = max(B.Plan(s.n, s.order_max, "bf16x3", support_max=s.support_max).workspace_bytes
+                  for s in ss)
     b = B.Batch(ss, budget_bytes=biggest + (1 << 20))
     assert b.report["waves"] >= 2
     assert b.report["workspace_bytes"] <= one["workspace_bytes"]
