@@ -105,17 +105,23 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
             v4f sr[2], si[2], srl[2], sil[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) sr[u] = si[u] = srl[u] = sil[u] = v4f{0, 0, 0, 0};
+            // The first 16-row tile is skipped when all its t are below last(p) (its h is 0).
+            auto gemm1 = [&](auto first) {
+                constexpr int U0 = decltype(first)::value;
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc)
+                for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    Split3 pr, pi;
-                    phi_frags<NP>(Lphi, kc * 32, t0 + 16 * u + c, g, pr, pi);
-                    mm6s(pr, xr[kc], sr[u], srl[u]);
-                    mm6s(pi, xn_[kc], sr[u], srl[u]);
-                    mm6s(pr, xi[kc], si[u], sil[u]);
-                    mm6s(pi, xr[kc], si[u], sil[u]);
-                }
+                    for (int u = U0; u < 2; ++u) {
+                        Split3 pr, pi;
+                        phi_frags<NP>(Lphi, kc * 32, t0 + 16 * u + c, g, pr, pi);
+                        mm6s(pr, xr[kc], sr[u], srl[u]);
+                        mm6s(pi, xn_[kc], sr[u], srl[u]);
+                        mm6s(pr, xi[kc], si[u], sil[u]);
+                        mm6s(pi, xr[kc], si[u], sil[u]);
+                    }
+            };
+            if (t0 + 16 > m) gemm1(std::integral_constant<int, 0>{});
+            else gemm1(std::integral_constant<int, 1>{});
             // Divisor and division (FP64 divisor) into the A operand of the reduction.
             float hre[8], him[8];
 #pragma unroll

@@ -135,6 +135,9 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
         v4f sr[2], si[2], srl[2], sil[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) sr[u] = si[u] = srl[u] = sil[u] = v4f{0, 0, 0, 0};
+        // The first 16-row tile is skipped when all its t are below last(p) (its h is 0).
+        auto gemm1 = [&](auto first) {
+        constexpr int U0 = decltype(first)::value;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
             float2 nxt[8];
@@ -144,7 +147,7 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
             split_x(cur, xr, xi);
             const Split3 xng = negx3(xi);
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
+            for (int u = U0; u < 2; ++u) {
                 const int pidx = ((kc * 4 + g) * 32 + 16 * u + c) * 8;
                 Split3 pr, pi;
                 pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PLP + pidx);
@@ -161,6 +164,9 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
 #pragma unroll
             for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
         }
+        };
+        if (t_base + 16 > m) gemm1(std::integral_constant<int, 0>{});
+        else gemm1(std::integral_constant<int, 1>{});
         // Divisor (FP64) and division into the reduction's A operand.
         float hre[8], him[8];
 #pragma unroll
