@@ -35,10 +35,11 @@ def log(*a):
 
 
 # Workspace cap per workload and precision (the memory limit of Alg. 1, applied to HBM);
-# 0 = none.  The n=200 workload needs 16-mode blocks of 5.4 GB (FP32 operands) or 10.8 GB
-# (FP64) per mode.
+# 0 = none.  The n=200 workload needs 5.4 GB (FP32 operands) or 10.8 GB (FP64) of chain
+# buffers per output mode: 176 GB gives 7 blocks of 29 modes (FP32 operands), 192 GB 13
+# blocks of 16 (FP64); the device holds 288 GB.
 WORKLOAD_BUDGET = {"n128-o4-dense-resonant": {"*": 64 << 30},
-                   "n200-o4-dense-hash": {"*": 96 << 30, "fp64": 192 << 30}}
+                   "n200-o4-dense-hash": {"*": 176 << 30, "fp64": 192 << 30}}
 
 
 def budget_for(workload, precision):
@@ -132,9 +133,10 @@ def sysm_support(sysm):
     return getattr(sysm, "support_max", 0) or 8
 
 
-def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0):
+def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0, progress=False):
     """Time `steps` steps on a dedicated stream (graph replay after the first call), then,
-    if `profile`, run the same steps eagerly with HIP events around every kernel launch."""
+    if `profile`, run the same steps eagerly with HIP events around every kernel launch.
+    With `progress` (multi-second steps) every step is synchronised and logged."""
     import torch
     from paper_2509_08968_amd import binding as B
 
@@ -151,18 +153,24 @@ def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0):
         plan.run(sysm.tensors, sysm.U, sysm.V, sysm.lam, ws, P, npf, stream)
 
     torch.cuda.synchronize()
-    for _ in range(warmup):
+    for w in range(warmup):
         p = mk()
         step(p)
         p.close()
+        if progress:
+            torch.cuda.synchronize()
+            log(f"[bench] {precision} warmup step {w + 1}/{warmup} done")
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
+    for i in range(steps):
         p = mk()                       # Alg. 1 block sizing is part of every step
         step(p)
         p.close()
+        if progress:
+            torch.cuda.synchronize()
+            log(f"[bench] {precision} step {i + 1}/{steps} done")
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -174,11 +182,14 @@ def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0):
         plans = []
         e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e2.record(stream)
-        for _ in range(steps):
+        for i in range(steps):
             p = mk()
             p.profile(True)            # eager launches, an event pair around each kernel
             step(p)
             plans.append(p)
+            if progress:
+                torch.cuda.synchronize()
+                log(f"[bench] {precision} profiled step {i + 1}/{steps} done")
         e3.record(stream)
         torch.cuda.synchronize()
         out["eager_ms_per_step"] = e2.elapsed_time(e3) / steps
@@ -380,6 +391,10 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="timed steps of the FP64 comparison (default: --steps)")
+    ap.add_argument("--fp64-warmup", type=int, default=None,
+                    help="warmup steps of the FP64 comparison (default: --warmup)")
     ap.add_argument("--no-tune", action="store_true", help="batch workload: skip the autotuner")
     ap.add_argument("--no-solo", action="store_true", help="batch workload: skip per-system runs")
     args = ap.parse_args()
@@ -434,8 +449,9 @@ def main():
         e["npf"] = rel(r["npf"][:, modes], ref_npf)
         return e
 
+    progress = s.n > 128
     res = time_path(sysm, s, args.precision, args.steps, args.warmup, device,
-                    not args.no_profile, budget_for(args.workload, args.precision))
+                    not args.no_profile, budget_for(args.workload, args.precision), progress)
     plan = res["plan"]
     entries = plan.modal_entries
     value = entries / (res["ms_per_step"] * 1e-3)
@@ -445,12 +461,15 @@ def main():
     fp64 = None
     if args.precision != "fp64" and not args.no_fp64:
         torch.cuda.empty_cache()
-        r64 = time_path(sysm, s, "fp64", args.steps, args.warmup, device, False,
-                        budget_for(args.workload, "fp64"))
+        st64 = args.steps if args.fp64_steps is None else args.fp64_steps
+        wu64 = args.warmup if args.fp64_warmup is None else args.fp64_warmup
+        r64 = time_path(sysm, s, "fp64", st64, wu64, device, False,
+                        budget_for(args.workload, "fp64"), progress)
         v64 = entries / (r64["ms_per_step"] * 1e-3)
         e64 = errors(r64)
         fp64 = {"value": v64, "ms_per_step": r64["ms_per_step"], "rel_err": e64,
-                "speedup_of_selected": v64 and value / v64}
+                "speedup_of_selected": v64 and value / v64, "steps": st64, "warmup": wu64,
+                "budget_bytes": budget_for(args.workload, "fp64")}
         log(f"[bench] fp64: {r64['ms_per_step']:.3f} ms/step, {v64:.3e} entries/s, err {e64}")
 
     roof = None
