@@ -8,9 +8,10 @@ roofline.traffic while the kernel sources are unchanged.
 Counter scaling: bench.py --copy-probe-mib X runs one device copy of X MiB before the
 workload; the factor that maps that copy's FETCH_SIZE (resp. WRITE_SIZE) to X MiB is
 applied to every dispatch.  Dispatches are named by the launch order of npf_run, which is
-fixed for a plan: prepare; per order M and mode block: the upper-index contraction (two
-launches for sparse tensors: clear + scatter), stages 1..M-1, the fused last stage, two
-partial-sum launches; finalize.
+fixed for a plan: prepare; per order M: the per-row tables (when the lower indices go
+first); per mode block: the upper-index contraction (two launches for sparse tensors: clear +
+scatter) and stages 1..M-1, or the per-row Psi step; the fused last stage; one partial-sum
+launch; finalize.
 
 usage: python -m paper_2509_08968_amd.counters WORKLOAD PRECISION FETCH_CSV WRITE_CSV
            COPY_MIB TRACE_STATS_CSV OUT_DIR "COMMAND TEXT"
@@ -48,7 +49,7 @@ def launch_names(workload: str, precision: str, budget: int = 0):
                 names.append(f"o{M}_psi_a")
             if not tucker:
                 names += [f"o{M}_stage{i}" for i in range(1, M)]
-            names += [f"o{M}_fused", f"o{M}_reduce.l1", f"o{M}_reduce.l2"]
+            names += [f"o{M}_fused", f"o{M}_reduce"]
     names.append("finalize")
     plan.close()
     return names

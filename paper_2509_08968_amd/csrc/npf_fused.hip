@@ -392,50 +392,46 @@ fused_last(FusedArgs a)
 // Partial sums in a fixed order, two levels: level 1 sums runs of 16 partials per element
 // (coalesced over k), level 2 sums the level-1 results into rows [j0, j0+J) of P_M and
 // adds P_M into the running sum over orders.
-constexpr int kRun = 16;
 
+// One launch: 32 outputs (j, k) per workgroup, eight fixed ranges of slots per output summed
+// by eight threads, the eight partial sums added in order -- the same result for any grid.
 __global__ void __launch_bounds__(256)
-reduce_parts_l1(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, int64_t J,
-                int64_t n, double2 *__restrict__ out)
+reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, int64_t J,
+             int64_t n, int64_t j0, double2 *__restrict__ P, double2 *__restrict__ psum, int first)
 {
+    __shared__ double2 part[8][32];
     const int64_t per = J * n;
-    const int64_t nrun = (nparts + kRun - 1) / kRun;
-    const int64_t total = nrun * per;
-    for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
-         x += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t q = x / per, e = x % per;
-        const int64_t j = e / n, k = e % n;
+    const int el = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int64_t chunk = (nparts + 7) / 8;
+    for (int64_t e0 = int64_t(blockIdx.x) * 32; e0 < per; e0 += int64_t(gridDim.x) * 32) {
+        const int64_t e = e0 + el;
         double sr = 0.0, si = 0.0;
-        const int64_t b1 = (q + 1) * kRun < nparts ? (q + 1) * kRun : nparts;
-        for (int64_t b = q * kRun; b < b1; ++b) {
-            const double2 v = parts[(b * Jpad + j) * n + k];
-            sr += v.x;
-            si += v.y;
+        if (e < per) {
+            const int64_t j = e / n, k = e % n;
+            const int64_t b1 = (grp + 1) * chunk < nparts ? (grp + 1) * chunk : nparts;
+            for (int64_t b = grp * chunk; b < b1; ++b) {
+                const double2 v = parts[(b * Jpad + j) * n + k];
+                sr += v.x;
+                si += v.y;
+            }
         }
-        out[x] = make_double2(sr, si);
-    }
-}
-
-__global__ void __launch_bounds__(256)
-reduce_parts_l2(const double2 *__restrict__ l1, int64_t nrun, int64_t J, int64_t n, int64_t j0,
-                double2 *__restrict__ P, double2 *__restrict__ psum, int first)
-{
-    const int64_t per = J * n;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < per;
-         e += int64_t(gridDim.x) * blockDim.x) {
-        double sr = 0.0, si = 0.0;
-        for (int64_t q = 0; q < nrun; ++q) {
-            const double2 v = l1[q * per + e];
-            sr += v.x;
-            si += v.y;
+        part[grp][el] = make_double2(sr, si);
+        __syncthreads();
+        if (grp == 0 && e < per) {
+            double tr = 0.0, ti = 0.0;
+            for (int q = 0; q < 8; ++q) {
+                tr += part[q][el].x;
+                ti += part[q][el].y;
+            }
+            P[j0 * n + e] = make_double2(tr, ti);
+            if (first) {
+                psum[j0 * n + e] = make_double2(tr, ti);
+            } else {
+                const double2 o = psum[j0 * n + e];
+                psum[j0 * n + e] = make_double2(o.x + tr, o.y + ti);
+            }
         }
-        P[j0 * n + e] = make_double2(sr, si);
-        if (first) {
-            psum[j0 * n + e] = make_double2(sr, si);
-        } else {
-            const double2 o = psum[j0 * n + e];
-            psum[j0 * n + e] = make_double2(o.x + sr, o.y + si);
-        }
+        __syncthreads();
     }
 }
 
@@ -567,18 +563,12 @@ hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
                                  double *P, double *psum, bool first, char *ws, hipStream_t s)
 {
-    const int64_t nrun = (nparts + kRun - 1) / kRun;
     const int64_t per = J * p->n;
-    auto blocks = [](int64_t work) {
-        int64_t b = (work + 255) / 256;
-        return unsigned(b < 1 ? 1 : (b > 8192 ? 8192 : b));
-    };
-    double2 *l1 = reinterpret_cast<double2 *>(ws + p->lay.parts2);
-    hipLaunchKernelGGL(reduce_parts_l1, dim3(blocks(nrun * per)), dim3(256), 0, s,
+    int64_t wg = (per + 31) / 32;
+    if (wg > 4096) wg = 4096;
+    hipLaunchKernelGGL(reduce_parts, dim3(unsigned(wg)), dim3(256), 0, s,
                        reinterpret_cast<const double2 *>(ws + p->lay.parts), nparts, p->Jpad, J,
-                       p->n, l1);
-    hipLaunchKernelGGL(reduce_parts_l2, dim3(blocks(per)), dim3(256), 0, s, l1, nrun, J, p->n, j0,
-                       reinterpret_cast<double2 *>(P), reinterpret_cast<double2 *>(psum),
+                       p->n, j0, reinterpret_cast<double2 *>(P), reinterpret_cast<double2 *>(psum),
                        first ? 1 : 0);
     return hipGetLastError();
 }

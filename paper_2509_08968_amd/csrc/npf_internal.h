@@ -53,8 +53,6 @@ struct Layout {
     int64_t phi_bytes = 0;
     int64_t parts = 0;           // per-workgroup partial P of the fused kernel
     int64_t parts_bytes = 0;
-    int64_t parts2 = 0;          // first-level sums of the partials
-    int64_t parts2_bytes = 0;
     TuckerLayout tk;
     int64_t total = 0;
 };

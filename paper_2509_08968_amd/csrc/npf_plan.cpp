@@ -58,8 +58,6 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     const int64_t nparts = std::max<int64_t>(1, fused_max_slots(&p, Jpad));
     L.parts_bytes = nparts * Jpad * p.n * 16;
     L.parts = take(L.parts_bytes);
-    L.parts2_bytes = ((nparts + 15) / 16) * Jpad * p.n * 16;
-    L.parts2 = take(L.parts2_bytes);
     const int smax = p.prob.support_max;
     if (smax >= 1 && smax <= kTuckerMaxSupport && p.N >= 2) {
         const int Mt = std::min(p.N, 3);          // the route serves orders 2 and 3
