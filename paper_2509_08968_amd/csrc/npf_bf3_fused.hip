@@ -5,28 +5,34 @@ namespace npf {
 
 namespace {
 
-constexpr int kThreads = kBf3Threads;
+constexpr int kThreads = 512;              // eight waves
 
 // ------------------------------------------------------------------ fused last stage
+// Eight waves: wave w owns the 16 modes of j-tile w % 4 and half h = w / 4 of the work --
+// the 16-row t-tile h of each 32-row chunk in the first product, the k-tiles of half h in
+// the reduction.  The two halves of a chunk's h meet in LDS (one barrier per chunk, the
+// exchange buffer alternating), so no product is computed twice and each wave holds half of
+// the reduction's accumulators: two waves per SIMD fit in the register file.
 template <int NP, int M>
 __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos bp)
 {
     constexpr int NKT = NP / 16, KC = NP / 32, N2 = NP * NP;
+    constexpr int KTW = NKT / 2;           // k-tiles per wave
     extern __shared__ __align__(16) char lds[];
     __bf16 *Lphi = reinterpret_cast<__bf16 *>(lds);
     __bf16 *Lz = reinterpret_cast<__bf16 *>(lds + 12 * N2);
-    float2 *Lz32 = reinterpret_cast<float2 *>(lds + 24 * N2);
-    double2 *Llam = reinterpret_cast<double2 *>(lds + 32 * N2);
+    double2 *Llam = reinterpret_cast<double2 *>(lds + 24 * N2);
+    float2 *Lx = reinterpret_cast<float2 *>(lds + 24 * N2 + 16 * NP);   // [2][4][2][4][64]
     copy_to_lds<NP>(lds, a.phiE, 12 * N2);
     copy_to_lds<NP>(lds + 12 * N2, a.zetaE, 12 * N2);
-    copy_to_lds<NP>(lds + 24 * N2, a.zeta32, 8 * N2);
     for (int t = threadIdx.x; t < NP; t += blockDim.x)
         Llam[t] = t < a.n ? a.lam[t] : make_double2(0.0, 0.0);
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int jt = wave & 3, half = wave >> 2;
     const int g = lane >> 4, c = lane & 15;
-    const int64_t jw = int64_t(bp.y) * 64 + wave * 16;
+    const int64_t jw = int64_t(bp.y) * 64 + jt * 16;
     const bool wave_on = jw < a.Jpad;
     const int64_t jl = jw + c;
     const bool j_ok = wave_on && jl < a.J;
@@ -34,48 +40,31 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
     // Below this |D|^2 (FP32) the divisor is finished in FP64: the tau band, and a margin
     // around eps so that the clamp is decided in FP64 exactly as specified.
     const float guard = fmaxf(float(a.tau2), float(4.0 * a.eps * a.eps));
+    const int nn = int(a.n), jp = int(a.Jpad);
 
-    double pacc_r[NKT][4], pacc_i[NKT][4];
+    double pacc_r[KTW][4], pacc_i[KTW][4];
 #pragma unroll
-    for (int kt = 0; kt < NKT; ++kt)
+    for (int kk = 0; kk < KTW; ++kk)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pacc_r[kt][r] = pacc_i[kt][r] = 0.0;
+        for (int r = 0; r < 4; ++r) pacc_r[kk][r] = pacc_i[kk][r] = 0.0;
 
     const float2 *X = static_cast<const float2 *>(a.X);
-    float2 xn[KC][8];
-    auto load_x = [&](int64_t it) {
-        const float2 *Xp = X + it * a.n * a.Jpad + jw + c;
-        const int jp = int(a.Jpad), nn = int(a.n);
+    int buf = 0;
+    // Items are the same for all eight waves (the barriers below are workgroup-uniform).
+    for (int64_t it = bp.x; it < a.items; it += bp.gx) {
+        const uint64_t pk = a.ptab[it];
+        // The item's rows stay in FP32 (split per chunk of the first product when used).
+        float2 xv[KC][8];
+        {
+            const float2 *Xp = X + it * a.n * a.Jpad + jw + c;
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc)
+            for (int kc = 0; kc < KC; ++kc)
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int ar = kc * 32 + 8 * g + s;
-                xn[kc][s] = ar < nn ? Xp[ar * jp] : make_float2(0.f, 0.f);
-            }
-    };
-    int64_t it = bp.x;
-    uint64_t pk_next = 0;
-    if (wave_on && it < a.items) {
-        load_x(it);
-        pk_next = a.ptab[it];
-    }
-    if (wave_on)
-    for (; it < a.items; it += bp.gx) {
-        // Split this item's rows, then start loading the next item's into the same registers.
-        Split3 xr[KC], xi[KC], xn_[KC];
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            split_x(xn[kc], xr[kc], xi[kc]);
-            xn_[kc] = negx3(xi[kc]);
+                for (int s = 0; s < 8; ++s) {
+                    const int ar = kc * 32 + 8 * g + s;
+                    xv[kc][s] = (wave_on && ar < nn) ? Xp[ar * jp] : make_float2(0.f, 0.f);
+                }
         }
-        const uint64_t pk = pk_next;
-        const int64_t itn = it + bp.gx;
-        if (itn < a.items) {
-            load_x(itn);
-            pk_next = a.ptab[itn];
-        }
-        // Item constants (M is a compile-time constant: the tuple lives in registers).
         int32_t p[M - 1];
 #pragma unroll
         for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
@@ -96,40 +85,36 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
         const double w_gt = -1.0 / den, w_eq = -1.0 / (den * double(run + 1));
         const float w_gt_f = float(w_gt), w_eq_f = float(w_eq);
 
-        v4f rr[NKT], ri[NKT], rrl[NKT], ril[NKT];
+        v4f rr[KTW], ri[KTW], rrl[KTW], ril[KTW];
 #pragma unroll
-        for (int kt = 0; kt < NKT; ++kt) rr[kt] = ri[kt] = rrl[kt] = ril[kt] = v4f{0, 0, 0, 0};
+        for (int kk = 0; kk < KTW; ++kk) rr[kk] = ri[kk] = rrl[kk] = ril[kk] = v4f{0, 0, 0, 0};
 
         for (int tc = m / 32; tc < KC; ++tc) {
-            const int t0 = tc * 32;
-            v4f sr[2], si[2], srl[2], sil[2];
+            const int t0 = tc * 32, tb = t0 + 16 * half;
+            // First product for this wave's 16-row tile (skipped when all its t < last(p)).
+            v4f sr = v4f{0, 0, 0, 0}, si = sr, srl = sr, sil = sr;
+            if (wave_on && tb + 16 > m) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) sr[u] = si[u] = srl[u] = sil[u] = v4f{0, 0, 0, 0};
-            // The first 16-row tile is skipped when all its t are below last(p) (its h is 0).
-            auto gemm1 = [&](auto first) {
-                constexpr int U0 = decltype(first)::value;
+                for (int kc = 0; kc < KC; ++kc) {
+                    Split3 xr, xi;
+                    split_x(xv[kc], xr, xi);
+                    const Split3 xng = negx3(xi);
+                    Split3 pr, pi;
+                    phi_frags<NP>(Lphi, kc * 32, tb + c, g, pr, pi);
+                    mm6s(pr, xr, sr, srl);
+                    mm6s(pi, xng, sr, srl);
+                    mm6s(pr, xi, si, sil);
+                    mm6s(pi, xr, si, sil);
+                }
+            }
+            // Divisor and division (FP64 divisor) for the tile's rows t = tb + 4g + r.
+            // exchange layout [buf][jt][half][r][lane]: lane-contiguous, no bank conflicts
+            float2 *xo = Lx + ((buf * 4 + jt) * 2 + half) * 4 * 64 + lane;
 #pragma unroll
-                for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-                    for (int u = U0; u < 2; ++u) {
-                        Split3 pr, pi;
-                        phi_frags<NP>(Lphi, kc * 32, t0 + 16 * u + c, g, pr, pi);
-                        mm6s(pr, xr[kc], sr[u], srl[u]);
-                        mm6s(pi, xn_[kc], sr[u], srl[u]);
-                        mm6s(pr, xi[kc], si[u], sil[u]);
-                        mm6s(pi, xr[kc], si[u], sil[u]);
-                    }
-            };
-            if (t0 + 16 > m) gemm1(std::integral_constant<int, 0>{});
-            else gemm1(std::integral_constant<int, 1>{});
-            // Divisor and division (FP64 divisor) into the A operand of the reduction.
-            float hre[8], him[8];
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int u = s >> 2, r = s & 3;
-                const int t = t0 + 16 * u + 4 * g + r;
+            for (int r = 0; r < 4; ++r) {
+                const int t = tb + 4 * g + r;
                 float vr = 0.f, vi = 0.f;
-                if (j_ok && t >= m && t < a.n) {
+                if (j_ok && t >= m && t < nn) {
                     // D in FP64 in the fixed summation order; the clamp and the division
                     // run in FP64 below the guard (|D| < tau, or near eps), else in FP32.
                     const double2 acc = add_fp64(lam_p, Llam[t]);
@@ -137,7 +122,7 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
                     const float dx = float(d.x), dy = float(d.y);
                     const float dd = dx * dx + dy * dy;
                     const float w = (t == m) ? w_eq_f : w_gt_f;
-                    const float sx = sr[u][r] + srl[u][r], sy = si[u][r] + sil[u][r];
+                    const float sx = sr[r] + srl[r], sy = si[r] + sil[r];
                     if (dd < guard) {
                         const double2 dc = divisor_fp64(acc, lam_j, a.eps);
                         const double f = ((t == m) ? w_eq : w_gt) / (dc.x * dc.x + dc.y * dc.y);
@@ -151,55 +136,66 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
                         vi = (sy * dx - sx * dy) * f;
                     }
                 }
-                hre[s] = vr;
-                him[s] = vi;
+                xo[r * 64] = make_float2(vr, vi);
             }
+            __syncthreads();
+            // The reduction's A operand: K slots s < 4 from tile 0, s >= 4 from tile 1.
+            const float2 *xin = Lx + (buf * 4 + jt) * 2 * 4 * 64 + lane;
+            float hre[8], him[8];
+#pragma unroll
+            for (int s8 = 0; s8 < 8; ++s8) {
+                const float2 v = xin[s8 * 64];          // (half, r) = (s8 / 4, s8 % 4)
+                hre[s8] = v.x;
+                him[s8] = v.y;
+            }
+            buf ^= 1;
+            if (!wave_on) continue;
             const Split3 ar_ = split8(hre), ai_ = split8(him);
             const Split3 an_ = negx3(ai_);
 #pragma unroll
-            for (int kt = 0; kt < NKT; ++kt) {
-                const int k = kt * 16 + c;
+            for (int kk = 0; kk < KTW; ++kk) {
+                const int k = (half * KTW + kk) * 16 + c;
                 const int z0 = int(zeta_frag_index(t0 + 4 * g, k, NP));
                 auto ld = [&](int pl) { return *reinterpret_cast<const v8bf *>(Lz + pl * N2 + z0); };
                 Split3 zr_, zi_;
                 zr_.h = ld(0); zr_.m = ld(1); zr_.l = ld(2);
                 zi_.h = ld(3); zi_.m = ld(4); zi_.l = ld(5);
-                mm6s(ar_, zr_, rr[kt], rrl[kt]);
-                mm6s(an_, zi_, rr[kt], rrl[kt]);
-                mm6s(ar_, zi_, ri[kt], ril[kt]);
-                mm6s(ai_, zr_, ri[kt], ril[kt]);
+                mm6s(ar_, zr_, rr[kk], rrl[kk]);
+                mm6s(an_, zi_, rr[kk], rrl[kk]);
+                mm6s(ar_, zi_, ri[kk], ril[kk]);
+                mm6s(ai_, zr_, ri[kk], ril[kk]);
             }
         }
-        // P += zp * R in FP64, zp[k] = prod_i zeta[p_i][k].
+        if (!wave_on) continue;
+        // P += zp * R in FP64, zp[k] = prod_i zeta[p_i][k] (FP32 product, one rounding per
+        // item; the sum over items is kept in FP64).
 #pragma unroll
-        for (int kt = 0; kt < NKT; ++kt) {
-            const int k = kt * 16 + c;
-            float2 z = Lz32[p[0] * NP + k];
+        for (int kk = 0; kk < KTW; ++kk) {
+            const int k = (half * KTW + kk) * 16 + c;
+            float2 z = a.zeta32[p[0] * NP + k];
 #pragma unroll
             for (int q = 1; q < M - 1; ++q) {
-                const float2 w = Lz32[p[q] * NP + k];
+                const float2 w = a.zeta32[p[q] * NP + k];
                 z = make_float2(z.x * w.x - z.y * w.y, z.x * w.y + z.y * w.x);
             }
-            // The item's product zp * R is formed in FP32 (one rounding); the sum over
-            // items is kept in FP64.
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const float vr = rr[kt][r] + rrl[kt][r], vi = ri[kt][r] + ril[kt][r];
-                pacc_r[kt][r] += double(vr * z.x - vi * z.y);
-                pacc_i[kt][r] += double(vr * z.y + vi * z.x);
+                const float vr = rr[kk][r] + rrl[kk][r], vi = ri[kk][r] + ril[kk][r];
+                pacc_r[kk][r] += double(vr * z.x - vi * z.y);
+                pacc_i[kk][r] += double(vr * z.y + vi * z.x);
             }
         }
     }
     if (!wave_on) return;
     double2 *dst = a.parts + int64_t(bp.x) * a.Jpad * a.n;
 #pragma unroll
-    for (int kt = 0; kt < NKT; ++kt) {
-        const int64_t k = kt * 16 + c;
+    for (int kk = 0; kk < KTW; ++kk) {
+        const int64_t k = (half * KTW + kk) * 16 + c;
         if (k >= a.n) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t j = jw + 4 * g + r;
-            dst[j * a.n + k] = make_double2(pacc_r[kt][r], pacc_i[kt][r]);
+            dst[j * a.n + k] = make_double2(pacc_r[kk][r], pacc_i[kk][r]);
         }
     }
 }
@@ -233,7 +229,7 @@ hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, c
 {
     const Bf3Args a = fused_args(p, M, j0, J, lam, ws);
     const dim3 grid{unsigned(groups), unsigned((p->Jpad + 63) / 64), 1u};
-    const size_t shm = size_t(32 * p->npad * p->npad + 16 * p->npad);
+    const size_t shm = size_t(24 * p->npad * p->npad + 16 * p->npad + 32768);
 #define NPF_FUSED_CASE(NP_, M_)                                                   \
     if (p->npad == NP_ && M == M_) {                                             \
         set_lds_limit(fused_bf3<NP_, M_>, int(shm));                              \
@@ -252,7 +248,7 @@ hipError_t launch_fused_bf3(const npf_plan_s *p, int M, int64_t j0, int64_t J, c
 hipError_t launch_fused_bf3_multi(int npad, int M, const MultiLaunch &m)
 {
     const dim3 grid{unsigned(m.groups), unsigned(m.gy), 1u};
-    const size_t shm = size_t(32 * npad * npad + 16 * npad);
+    const size_t shm = size_t(24 * npad * npad + 16 * npad + 32768);
     const Bf3Args *as = static_cast<const Bf3Args *>(m.args);
 #define NPF_FUSED_MULTI(NP_, M_)                                                           \
     if (npad == NP_ && M == M_) {                                                         \
