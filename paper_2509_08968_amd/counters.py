@@ -11,7 +11,7 @@ applied to every dispatch.  Dispatches are named by the launch order of npf_run,
 fixed for a plan: prepare; per order M: the per-row tables (when the lower indices go
 first); per mode block: the upper-index contraction (two launches for sparse tensors: clear +
 scatter) and stages 1..M-1, or the per-row Psi step; the fused last stage; one partial-sum
-launch; finalize.
+launch (which also writes the NPF for the last order).
 
 usage: python -m paper_2509_08968_amd.counters WORKLOAD PRECISION FETCH_CSV WRITE_CSV
            COPY_MIB TRACE_STATS_CSV OUT_DIR "COMMAND TEXT"
@@ -50,7 +50,6 @@ def launch_names(workload: str, precision: str, budget: int = 0):
             if not tucker:
                 names += [f"o{M}_stage{i}" for i in range(1, M)]
             names += [f"o{M}_fused", f"o{M}_reduce"]
-    names.append("finalize")
     plan.close()
     return names
 

@@ -340,18 +340,15 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
                                "fused last stage");
             }
             if (!rc) {
+                // The last order's partial sums also write the NPF (Alg. 2 step 20).
+                const NpfOut fin{static_cast<const double *>(U), static_cast<const double *>(V),
+                                 static_cast<double *>(npf_out)};
                 Timed t(plan, kname(M, "reduce"), s);
-                rc = check_hip(launch_reduce_parts(plan, M, j0, J, PM, psum, M == 2, w, s),
+                rc = check_hip(launch_reduce_parts(plan, M, j0, J, PM, psum, M == 2, w, s,
+                                                   (M == plan->N && npf_out) ? &fin : nullptr),
                                "partial sums");
             }
         }
-    }
-    if (!rc && npf_out) {
-        Timed t(plan, "finalize", s);
-        rc = check_hip(launch_finalize(plan, static_cast<const double *>(U),
-                                       static_cast<const double *>(V), psum,
-                                       static_cast<double *>(npf_out), s),
-                       "finalize");
     }
     return rc;
 }

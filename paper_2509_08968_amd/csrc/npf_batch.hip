@@ -201,24 +201,19 @@ int run_waves(npf_batch_s *b, const npf_tensor *A, const void *const *U, const v
                                      : reinterpret_cast<double *>(r + p->lay.pm);
                     const int64_t slots = groups_of(L, q) *
                                           (L.npad <= 64 ? 1 : fused_bf3_tr_slices(p, p->Jpad));
+                    const NpfOut fin{static_cast<const double *>(U[s]),
+                                     static_cast<const double *>(V[s]),
+                                     npf_out ? static_cast<double *>(npf_out[s]) : nullptr};
                     rc = check_hip(launch_reduce_parts_n(p, slots, 0, p->n, PM,
                                                          reinterpret_cast<double *>(r + p->lay.psum),
-                                                         M == 2, r, st),
+                                                         M == 2, r, st,
+                                                         (M == p->N && fin.npf) ? &fin : nullptr),
                                    "partial sums");
                     if (rc) return rc;
                 }
             }
         }
-        for (int s : ws_sys) {
-            if (!npf_out || !npf_out[s]) continue;
-            const npf_plan_s *p = b->sys[s].plan;
-            rc = check_hip(launch_finalize(p, static_cast<const double *>(U[s]),
-                                           static_cast<const double *>(V[s]),
-                                           reinterpret_cast<const double *>(region(s) + p->lay.psum),
-                                           static_cast<double *>(npf_out[s]), st),
-                           "finalize");
-            if (rc) return rc;
-        }
+
     }
     return rc;
 }
@@ -380,10 +375,10 @@ extern "C" int npf_batch_create(const npf_problem *problems, int64_t count, int6
     }
     b->table_bytes = std::max<int64_t>(off, 256);
     b->ws_bytes = b->table_bytes + b->wave_bytes;
-    // Launches per run: per system prepare, finalize and per order its upper-index
-    // contraction (two for sparse sources) and two partial-sum launches; plus the shared.
+    // Launches per run (about): per system prepare and per order its upper-index
+    // contraction (two for sparse sources) and one partial-sum launch; plus the shared.
     int64_t per = 0;
-    for (const Sys &s : b->sys) per += 2 + 4 * (s.plan->N - 1);   // Tucker orders: 2 + 2 as well
+    for (const Sys &s : b->sys) per += 1 + 3 * (s.plan->N - 1);
     b->launches = per + int64_t(b->shared.size()) + 1;
     *batch_out = b;
     return NPF_OK;

@@ -395,9 +395,14 @@ fused_last(FusedArgs a)
 
 // One launch: 32 outputs (j, k) per workgroup, eight fixed ranges of slots per output summed
 // by eight threads, the eight partial sums added in order -- the same result for any grid.
+// For the last order (npf non-null) the finished sum over orders also gives the NPF entry
+// NPF[k, j] = Phi[k, j] (delta Psi[j, k] + psum[j, k]) of Alg. 2 step 20 (the arithmetic of
+// finalize_simt).
 __global__ void __launch_bounds__(256)
 reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, int64_t J,
-             int64_t n, int64_t j0, double2 *__restrict__ P, double2 *__restrict__ psum, int first)
+             int64_t n, int64_t j0, double2 *__restrict__ P, double2 *__restrict__ psum, int first,
+             const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta,
+             double2 *__restrict__ npf)
 {
     __shared__ double2 part[8][32];
     const int64_t per = J * n;
@@ -424,11 +429,18 @@ reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, in
                 ti += part[q][el].y;
             }
             P[j0 * n + e] = make_double2(tr, ti);
-            if (first) {
-                psum[j0 * n + e] = make_double2(tr, ti);
-            } else {
+            double2 tot = make_double2(tr, ti);
+            if (!first) {
                 const double2 o = psum[j0 * n + e];
-                psum[j0 * n + e] = make_double2(o.x + tr, o.y + ti);
+                tot = make_double2(o.x + tr, o.y + ti);
+            }
+            psum[j0 * n + e] = tot;
+            if (npf) {
+                const int64_t j = j0 + e / n, k = e % n;
+                const double2 w = Psi[j * n + k];
+                double2 z = make_double2(delta * w.x, delta * w.y);
+                z = add_fp64(z, tot);
+                npf[k * n + j] = cmul(Phi[k * n + j], z);
             }
         }
         __syncthreads();
@@ -555,13 +567,15 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
 int64_t fused_default_groups(const npf_plan_s *p, int M) { return fused_gx(p, p->U[M - 1], p->Jpad); }
 
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
-                               double *psum, bool first, char *ws, hipStream_t s)
+                               double *psum, bool first, char *ws, hipStream_t s,
+                               const NpfOut *fin)
 {
-    return launch_reduce_parts_n(p, fused_groups(p, M), j0, J, P, psum, first, ws, s);
+    return launch_reduce_parts_n(p, fused_groups(p, M), j0, J, P, psum, first, ws, s, fin);
 }
 
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
-                                 double *P, double *psum, bool first, char *ws, hipStream_t s)
+                                 double *P, double *psum, bool first, char *ws, hipStream_t s,
+                                 const NpfOut *fin)
 {
     const int64_t per = J * p->n;
     int64_t wg = (per + 31) / 32;
@@ -569,7 +583,9 @@ hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0
     hipLaunchKernelGGL(reduce_parts, dim3(unsigned(wg)), dim3(256), 0, s,
                        reinterpret_cast<const double2 *>(ws + p->lay.parts), nparts, p->Jpad, J,
                        p->n, j0, reinterpret_cast<double2 *>(P), reinterpret_cast<double2 *>(psum),
-                       first ? 1 : 0);
+                       first ? 1 : 0, fin ? reinterpret_cast<const double2 *>(fin->V) : nullptr,
+                       fin ? reinterpret_cast<const double2 *>(fin->U) : nullptr, p->prob.delta,
+                       fin ? reinterpret_cast<double2 *>(fin->npf) : nullptr);
     return hipGetLastError();
 }
 

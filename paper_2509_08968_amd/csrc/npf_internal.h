@@ -156,8 +156,14 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
                              char *ws, hipStream_t s);
 // Sum of the partials of launch_fused_last into rows [j0, j0+J) of P (fixed order), and
 // psum = P (first order) or psum += P.
+// The NPF output written by the last order's partial sums (Alg. 2 step 20).
+struct NpfOut {
+    const double *U, *V;      // Psi, Phi
+    double *npf;
+};
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
-                               double *psum, bool first, char *ws, hipStream_t s);
+                               double *psum, bool first, char *ws, hipStream_t s,
+                               const NpfOut *fin = nullptr);
 int64_t fused_groups(const npf_plan_s *p, int M);
 // Most partial-P slots any order writes for a block of Jpad modes.
 int64_t fused_max_slots(const npf_plan_s *p, int64_t Jpad);
@@ -186,7 +192,8 @@ int fused_bf3_tr_kranges(int64_t npad);
 int stage_bf3_tr_tiles(int64_t npad);
 // Partial sums of a block's fused-kernel slots (nparts of them) into P rows and psum.
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
-                                 double *P, double *psum, bool first, char *ws, hipStream_t s);
+                                 double *P, double *psum, bool first, char *ws, hipStream_t s,
+                                 const NpfOut *fin = nullptr);
 int64_t fused_default_groups(const npf_plan_s *p, int M);
 bool bf3_tr_fused_supported(const npf_plan_s *p);
 int bf3_items_per_group(int64_t Jpad);
