@@ -13,8 +13,9 @@ first); per mode block: the upper-index contraction (two launches for sparse ten
 scatter) and stages 1..M-1, or the per-row Psi step; the fused last stage; one partial-sum
 launch (which also writes the NPF for the last order).
 
-usage: python -m paper_2509_08968_amd.counters WORKLOAD PRECISION FETCH_CSV WRITE_CSV
-           COPY_MIB TRACE_STATS_CSV OUT_DIR "COMMAND TEXT"
+usage: python -m paper_2509_08968_amd.counters trace WORKLOAD PRECISION STATS_CSV OUT_DIR CMD
+       python -m paper_2509_08968_amd.counters traffic WORKLOAD PRECISION FETCH_CSV WRITE_CSV
+           COPY_MIB OUT_DIR CMD...
 """
 from __future__ import annotations
 
@@ -90,8 +91,22 @@ def traffic(workload, precision, fetch_csv, write_csv, copy_mib, budget=0):
     return out
 
 
-def main(argv):
-    workload, precision, fetch_csv, write_csv, copy_mib, stats_csv, out_dir, cmd = argv[:8]
+def write_trace(workload, precision, stats_csv, out_dir, cmd):
+    """Kernel-trace statistics summary (profiles/kernel_trace_<workload>_<precision>.txt)."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# rocprofv3 kernel-trace statistics, {workload}, {precision}",
+             "# command (repo root, TMPDIR=/tmp):", f"#   {cmd}",
+             "# calls  total_ms  avg_us  min_us  max_us  pct  kernel"]
+    for r in rows:
+        lines.append(f"{int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
+                     f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}  {r['Name'][:100]}")
+    with open(os.path.join(out_dir, f"kernel_trace_{workload}_{precision}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def write_traffic(workload, precision, fetch_csv, write_csv, copy_mib, out_dir, cmds):
+    """HBM traffic summary and the per-launch JSON that bench.py reads."""
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
     budget = bench.budget_for(workload, precision)
@@ -103,26 +118,29 @@ def main(argv):
                   "for it; valid for the kernel sources with this digest"}
     with open(os.path.join(out_dir, f"traffic_{workload}_{precision}.json"), "w") as f:
         json.dump(js, f, indent=1)
+    first = next(iter(t.values()))
     lines = [f"# HBM traffic per launch, {workload}, {precision}",
-             f"# commands (repo root, TMPDIR=/tmp):", *[f"#   {c}" for c in cmd.split(" ;; ")],
+             "# commands (repo root, TMPDIR=/tmp):", *[f"#   {c}" for c in cmds],
              f"# counter scale factors (copy of {copy_mib} MiB): fetch "
-             f"{next(iter(t.values()))['fetch_scale']:.3f}, write {next(iter(t.values()))['write_scale']:.3f}",
+             f"{first['fetch_scale']:.3f}, write {first['write_scale']:.3f}",
              "# kernel  launches/step  fetch_GB  write_GB  symbol"]
     for nm, d in sorted(t.items(), key=lambda kv: -kv[1]["bytes_per_launch"]):
-        lines.append(f"{nm:18s} {d['launches_per_step']:3d} {d['fetch_bytes_per_launch'] / 1e9:10.4f} "
+        lines.append(f"{nm:24s} {d['launches_per_step']:3d} {d['fetch_bytes_per_launch'] / 1e9:10.4f} "
                      f"{d['write_bytes_per_launch'] / 1e9:10.4f}  {d['symbol']}")
     with open(os.path.join(out_dir, f"hbm_traffic_{workload}_{precision}.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
-    rows = list(csv.DictReader(open(stats_csv)))
-    lines = [f"# rocprofv3 kernel-trace statistics, {workload}, {precision}",
-             "# command (repo root, TMPDIR=/tmp):", f"#   {cmd.split(' ;; ')[0]}",
-             "# calls  total_ms  avg_us  min_us  max_us  pct  kernel"]
-    for r in rows:
-        lines.append(f"{int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
-                     f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
-                     f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}  {r['Name'][:100]}")
-    with open(os.path.join(out_dir, f"kernel_trace_{workload}_{precision}.txt"), "w") as f:
-        f.write("\n".join(lines) + "\n")
+
+
+def main(argv):
+    mode = argv[0]
+    if mode == "trace":
+        workload, precision, stats_csv, out_dir, cmd = argv[1:6]
+        write_trace(workload, precision, stats_csv, out_dir, cmd)
+    elif mode == "traffic":
+        workload, precision, fetch_csv, write_csv, copy_mib, out_dir = argv[1:7]
+        write_traffic(workload, precision, fetch_csv, write_csv, copy_mib, out_dir, argv[7:])
+    else:
+        raise SystemExit("usage: counters.py trace|traffic ...")
 
 
 if __name__ == "__main__":
