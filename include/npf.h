@@ -104,6 +104,11 @@ typedef struct npf_problem {
  * This flag disables that and always launches eagerly.  Graphs are never used on the
  * NULL stream, on a stream that is already capturing, or while profiling. */
 #define NPF_FLAG_NO_GRAPH 1
+/* When the plan has one block of modes and at least two orders, the orders' chains and last
+ * stages run concurrently inside the replayed graph, each in workspace of its own (the
+ * partial sums still run in order); this flag keeps them in sequence and the workspace
+ * smaller.  Eager runs are always sequential. */
+#define NPF_FLAG_SERIAL_ORDERS 2
 
 typedef struct npf_plan_s *npf_plan_t;
 

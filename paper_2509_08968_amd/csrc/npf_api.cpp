@@ -144,6 +144,7 @@ extern "C" int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block,
     hipStream_t s = static_cast<hipStream_t>(stream);
     int64_t b0, b1;
     block_range(plan, block, b0, b1);
+    const OrderLayout ol(plan, order);
     rc = stage_operands(plan, U, V, ws, s);
     const bool tucker = tucker_supported(plan, A, order);
     if (!rc && tucker) rc = run_rows(plan, order, A, V, ws, s);
@@ -230,7 +231,19 @@ namespace {
 
 // The launch sequence of npf_run (eager).
 int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
-              const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s);
+              const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s,
+              bool concurrent = false);
+
+// Side streams and events of a concurrent plan (made once, before the first capture).
+bool ensure_streams(npf_plan_t plan)
+{
+    if (plan->ev_prep) return true;
+    for (int M = 2; M < plan->N; ++M)
+        if (hipStreamCreateWithFlags(&plan->side[M], hipStreamNonBlocking) != hipSuccess) return false;
+    for (int M = 2; M <= plan->N; ++M)
+        if (hipEventCreateWithFlags(&plan->ev_done[M], hipEventDisableTiming) != hipSuccess) return false;
+    return hipEventCreateWithFlags(&plan->ev_prep, hipEventDisableTiming) == hipSuccess;
+}
 
 // Graph cache: one instantiated graph per distinct argument set (problem, descriptors,
 // pointers, stream), least recently used evicted.
@@ -288,9 +301,10 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
             e.used = ++g_graph_clock;
             return check_hip(hipGraphLaunch(e.exec, s), "graph launch");
         }
+    const bool conc = plan->concurrent && ensure_streams(plan);
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
-    rc = run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
+    rc = run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s, conc);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
     if (rc != NPF_OK) {
@@ -316,40 +330,57 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
 namespace {
 
 int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
-              const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s)
+              const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s,
+              bool concurrent)
 {
+    // Concurrent (captured runs of single-block plans with several orders): order M < N runs
+    // its chain and last stage on side stream M after the operand staging; the partial sums
+    // of every order run on the main stream, in order, after that order's last stage.
     int rc = NPF_OK;
     char *w = static_cast<char *>(ws);
     const int64_t nn = plan->n * plan->n;
-    double *psum = reinterpret_cast<double *>(w + plan->lay.psum);
-    double *pm = reinterpret_cast<double *>(w + plan->lay.pm);
     rc = stage_operands(plan, U, V, ws, s);
+    if (!rc && concurrent) rc = check_hip(hipEventRecord(plan->ev_prep, s), "fork");
+    auto reduce = [&](int M, int64_t j0, int64_t J, hipStream_t st) {
+        const OrderLayout ol(plan, M);
+        double *PM = P_out ? static_cast<double *>(P_out) + 2 * (M - 2) * nn
+                           : reinterpret_cast<double *>(w + plan->lay.pm);
+        double *psum = reinterpret_cast<double *>(w + plan->lay.psum);
+        // The last order's partial sums also write the NPF (Alg. 2 step 20).
+        const NpfOut fin{static_cast<const double *>(U), static_cast<const double *>(V),
+                         static_cast<double *>(npf_out)};
+        Timed t(plan, kname(M, "reduce"), st);
+        return check_hip(launch_reduce_parts(plan, M, j0, J, PM, psum, M == 2, w, st,
+                                             (M == plan->N && npf_out) ? &fin : nullptr),
+                         "partial sums");
+    };
     for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
-        double *PM = P_out ? static_cast<double *>(P_out) + 2 * (M - 2) * nn : pm;
+        const bool on_side = concurrent && M < plan->N;
+        const hipStream_t sm = on_side ? plan->side[M] : s;
+        if (on_side && (rc = check_hip(hipStreamWaitEvent(sm, plan->ev_prep, 0), "fork"))) break;
+        const OrderLayout ol(plan, M);
         const bool tucker = tucker_supported(plan, &A[M - 2], M);
-        if (tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, s);
+        if (tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, sm);
         for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
             int64_t j0, J;
             block_modes(plan, b, j0, J);
-            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, s, tucker);
+            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, sm, tucker);
             if (rc) break;
             {
-                Timed t(plan, kname(M, "fused"), s);
+                Timed t(plan, kname(M, "fused"), sm);
                 rc = check_hip(launch_fused_last(plan, M, j0, J,
-                                                 static_cast<const double *>(lambda), w, s),
+                                                 static_cast<const double *>(lambda), w, sm),
                                "fused last stage");
             }
-            if (!rc) {
-                // The last order's partial sums also write the NPF (Alg. 2 step 20).
-                const NpfOut fin{static_cast<const double *>(U), static_cast<const double *>(V),
-                                 static_cast<double *>(npf_out)};
-                Timed t(plan, kname(M, "reduce"), s);
-                rc = check_hip(launch_reduce_parts(plan, M, j0, J, PM, psum, M == 2, w, s,
-                                                   (M == plan->N && npf_out) ? &fin : nullptr),
-                               "partial sums");
-            }
+            if (!rc && !concurrent) rc = reduce(M, j0, J, s);
         }
+        if (!rc && concurrent) rc = check_hip(hipEventRecord(plan->ev_done[M], sm), "join");
     }
+    if (concurrent)
+        for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
+            rc = check_hip(hipStreamWaitEvent(s, plan->ev_done[M], 0), "join");
+            if (!rc) rc = reduce(M, 0, plan->n, s);
+        }
     return rc;
 }
 

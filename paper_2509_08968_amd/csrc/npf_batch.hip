@@ -297,6 +297,7 @@ extern "C" int npf_batch_create(const npf_problem *problems, int64_t count, int6
         }
         q.block_modes = 0;
         q.hbm_budget_bytes = 0;
+        q.flags |= NPF_FLAG_SERIAL_ORDERS;      // the batch runs each system's orders in turn
         npf_plan_t p = nullptr;
         const int rc = npf_plan_create(&q, &p);
         if (rc) {

@@ -87,9 +87,30 @@ struct npf_plan_s {
     int64_t npad = 0;                    // n rounded up to a multiple of 32
     int64_t esz = 16;                    // bytes per complex element of the chain
     npf::TupleTables tt;
-    npf::Layout lay;
+    npf::Layout lay;                     // the layout launches read (see OrderLayout)
     npf::Profiler prof;
+    // Concurrent orders: each order's chain buffers, partials, P scratch and per-row tables
+    // in workspace of its own (ord[M]); the shared parts (tuple tables, operands, psum) are
+    // common.  Side streams and events are made on the first captured run.
+    bool concurrent = false;
+    npf::Layout ord[NPF_MAX_ORDER + 1];
+    hipStream_t side[NPF_MAX_ORDER + 1] = {};
+    hipEvent_t ev_prep = nullptr, ev_done[NPF_MAX_ORDER + 1] = {};
+    ~npf_plan_s();
 };
+
+namespace npf {
+// While alive, launches of order M read the order's own layout (concurrent plans).
+struct OrderLayout {
+    npf_plan_s *plan;
+    Layout saved;
+    OrderLayout(npf_plan_s *p, int M) : plan(p), saved(p->lay)
+    {
+        if (p->concurrent) p->lay = p->ord[M];
+    }
+    ~OrderLayout() { plan->lay = saved; }
+};
+}  // namespace npf
 
 namespace npf {
 // Brackets one kernel launch with an event pair when the plan is profiling.

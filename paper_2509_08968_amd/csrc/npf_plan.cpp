@@ -74,9 +74,65 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     return L;
 }
 
+// Layout with a region per order for concurrent orders: common parts once, then for each
+// order M its chain buffers, partials, P scratch and per-row tables.  ord[M] are complete
+// layouts (the common offsets repeated); the returned layout's total covers all of them.
+static Layout make_split_layout(const npf_plan_s &p, int64_t Jpad, Layout *ord)
+{
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = off;
+        off += round_up(std::max<int64_t>(bytes, 0), 256);
+        return at;
+    };
+    Layout C;
+    C.ttab = take(p.tt.total * 8);
+    C.psum = take(p.n * p.n * 16);
+    C.phi_bytes = p.npad * p.npad * 16 * 4;
+    C.phi = take(C.phi_bytes);
+    const int64_t nparts = std::max<int64_t>(1, fused_max_slots(&p, Jpad));
+    const int smax = p.prob.support_max;
+    for (int M = 2; M <= p.N; ++M) {
+        Layout L = C;
+        int64_t per[2] = {0, 0};
+        for (int i = 0; i < M; ++i) per[i % 2] = std::max(per[i % 2], p.U[i] * p.U[M - i] * Jpad * p.esz);
+        L.buf_bytes[0] = per[0];
+        L.buf_bytes[1] = per[1];
+        L.buf[0] = take(per[0]);
+        L.buf[1] = take(per[1]);
+        L.pm = take(p.n * p.n * 16);
+        L.parts_bytes = nparts * Jpad * p.n * 16;
+        L.parts = take(L.parts_bytes);
+        if (tucker_route(&p, M)) {
+            L.tk.over = take(p.n * 4);
+            L.tk.S = take(p.n * smax * 4);
+            L.tk.cnt = take(p.n * 4);
+            L.tk.inv = take(p.n * p.n * 4);
+            L.tk.invcnt = take(p.n * 4);
+            L.tk.D = take(p.n * binom(smax + M - 1, M) * 8);
+            if (M == 3) L.tk.Y = take(p.n * smax * p.n * smax * 16);
+            L.tk.W = take(p.U[M - 1] * p.n * smax * 16);
+        }
+        ord[M] = L;
+    }
+    for (int M = 2; M <= p.N; ++M) ord[M].total = off;
+    Layout R = ord[p.N];
+    R.total = off;
+    return R;
+}
+
 }  // namespace npf
 
 using namespace npf;
+
+npf_plan_s::~npf_plan_s()
+{
+    for (auto &st : side)
+        if (st) (void)hipStreamDestroy(st);
+    for (auto &e : ev_done)
+        if (e) (void)hipEventDestroy(e);
+    if (ev_prep) (void)hipEventDestroy(ev_prep);
+}
 
 extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
 {
@@ -134,6 +190,16 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
     p->J = (q.n + p->n_blocks - 1) / p->n_blocks;
     p->Jpad = round_up(p->J, 16);
     p->lay = make_layout(*p, p->Jpad);
+    for (int M = 0; M <= NPF_MAX_ORDER; ++M) p->ord[M] = p->lay;
+    if (!(q.flags & NPF_FLAG_SERIAL_ORDERS) && p->n_blocks == 1 && p->N >= 3) {
+        Layout ord[NPF_MAX_ORDER + 1];
+        const Layout split = make_split_layout(*p, p->Jpad, ord);
+        if (q.hbm_budget_bytes == 0 || split.total <= q.hbm_budget_bytes) {
+            p->concurrent = true;
+            p->lay = split;
+            for (int M = 2; M <= p->N; ++M) p->ord[M] = ord[M];
+        }
+    }
     *plan_out = p;
     return NPF_OK;
 }
