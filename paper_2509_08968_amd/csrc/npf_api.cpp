@@ -98,7 +98,8 @@ int run_rows(const npf_plan_s *p, int M, const npf_tensor *A, const void *V, voi
 // T_{M-1} of the block [j0, j0 + J) in buffer (M-1) % 2: the upper-index contraction and
 // the chain stages, or Psi applied to the per-row tables (tucker: run_rows done).
 int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tensor *A,
-              const void *U, const void *V, void *ws, hipStream_t s, bool tucker = false)
+              const void *U, const void *V, void *ws, hipStream_t s, bool tucker = false,
+              hipEvent_t before_stages = nullptr)
 {
     if (tucker) {
         Timed t(p, kname(M, "tucker_psi"), s);
@@ -113,6 +114,9 @@ int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tenso
         Timed t(p, kname(M, "psi_a"), s);
         rc = check_hip(launch_psi_a(a), "upper-index contraction");
     }
+    // The upper-index contraction needs only the inputs; the stages also need the staged
+    // operands (concurrent runs stage them on another stream meanwhile).
+    if (!rc && before_stages) rc = check_hip(hipStreamWaitEvent(s, before_stages, 0), "join");
     const bool mfma = stage_mfma_supported(p);
     for (int i = 1; rc == NPF_OK && i < M; ++i) {
         Timed t(p, kname(M, "stage", i), s);
@@ -238,10 +242,11 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
 bool ensure_streams(npf_plan_t plan)
 {
     if (plan->ev_prep) return true;
-    for (int M = 2; M < plan->N; ++M)
+    for (int M = 1; M < plan->N; ++M)       // side[1]: operand staging; side[M]: order M
         if (hipStreamCreateWithFlags(&plan->side[M], hipStreamNonBlocking) != hipSuccess) return false;
     for (int M = 2; M <= plan->N; ++M)
         if (hipEventCreateWithFlags(&plan->ev_done[M], hipEventDisableTiming) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&plan->ev_start, hipEventDisableTiming) != hipSuccess) return false;
     return hipEventCreateWithFlags(&plan->ev_prep, hipEventDisableTiming) == hipSuccess;
 }
 
@@ -333,14 +338,21 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
               const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s,
               bool concurrent)
 {
-    // Concurrent (captured runs of single-block plans with several orders): order M < N runs
-    // its chain and last stage on side stream M after the operand staging; the partial sums
-    // of every order run on the main stream, in order, after that order's last stage.
+    // Concurrent (captured runs of single-block plans with several orders): the operands are
+    // staged on side stream 1 while every order starts its upper-index contraction; order
+    // M < N runs its chain and last stage on side stream M; the partial sums of every order
+    // run on the main stream, in order, after that order's last stage.
     int rc = NPF_OK;
     char *w = static_cast<char *>(ws);
     const int64_t nn = plan->n * plan->n;
-    rc = stage_operands(plan, U, V, ws, s);
-    if (!rc && concurrent) rc = check_hip(hipEventRecord(plan->ev_prep, s), "fork");
+    if (concurrent) {
+        rc = check_hip(hipEventRecord(plan->ev_start, s), "fork");
+        if (!rc) rc = check_hip(hipStreamWaitEvent(plan->side[1], plan->ev_start, 0), "fork");
+        if (!rc) rc = stage_operands(plan, U, V, ws, plan->side[1]);
+        if (!rc) rc = check_hip(hipEventRecord(plan->ev_prep, plan->side[1]), "fork");
+    } else {
+        rc = stage_operands(plan, U, V, ws, s);
+    }
     auto reduce = [&](int M, int64_t j0, int64_t J, hipStream_t st) {
         const OrderLayout ol(plan, M);
         double *PM = P_out ? static_cast<double *>(P_out) + 2 * (M - 2) * nn
@@ -357,14 +369,16 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
     for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
         const bool on_side = concurrent && M < plan->N;
         const hipStream_t sm = on_side ? plan->side[M] : s;
-        if (on_side && (rc = check_hip(hipStreamWaitEvent(sm, plan->ev_prep, 0), "fork"))) break;
+        if (on_side && (rc = check_hip(hipStreamWaitEvent(sm, plan->ev_start, 0), "fork"))) break;
         const OrderLayout ol(plan, M);
         const bool tucker = tucker_supported(plan, &A[M - 2], M);
-        if (tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, sm);
+        if (tucker && concurrent) rc = check_hip(hipStreamWaitEvent(sm, plan->ev_prep, 0), "join");
+        if (!rc && tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, sm);
         for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
             int64_t j0, J;
             block_modes(plan, b, j0, J);
-            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, sm, tucker);
+            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, sm, tucker,
+                           (concurrent && !tucker) ? plan->ev_prep : nullptr);
             if (rc) break;
             {
                 Timed t(plan, kname(M, "fused"), sm);

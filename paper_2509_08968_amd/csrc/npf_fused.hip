@@ -393,8 +393,8 @@ fused_last(FusedArgs a)
 // (coalesced over k), level 2 sums the level-1 results into rows [j0, j0+J) of P_M and
 // adds P_M into the running sum over orders.
 
-// One launch: 32 outputs (j, k) per workgroup, eight fixed ranges of slots per output summed
-// by eight threads, the eight partial sums added in order -- the same result for any grid.
+// One launch: 16 outputs (j, k) per workgroup, sixteen fixed ranges of slots per output
+// summed by sixteen threads, the partial sums added in order -- the same result for any grid.
 // For the last order (npf non-null) the finished sum over orders also gives the NPF entry
 // NPF[k, j] = Phi[k, j] (delta Psi[j, k] + psum[j, k]) of Alg. 2 step 20 (the arithmetic of
 // finalize_simt).
@@ -404,11 +404,11 @@ reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, in
              const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta,
              double2 *__restrict__ npf)
 {
-    __shared__ double2 part[8][32];
+    __shared__ double2 part[16][16];
     const int64_t per = J * n;
-    const int el = threadIdx.x & 31, grp = threadIdx.x >> 5;
-    const int64_t chunk = (nparts + 7) / 8;
-    for (int64_t e0 = int64_t(blockIdx.x) * 32; e0 < per; e0 += int64_t(gridDim.x) * 32) {
+    const int el = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    const int64_t chunk = (nparts + 15) / 16;
+    for (int64_t e0 = int64_t(blockIdx.x) * 16; e0 < per; e0 += int64_t(gridDim.x) * 16) {
         const int64_t e = e0 + el;
         double sr = 0.0, si = 0.0;
         if (e < per) {
@@ -424,7 +424,7 @@ reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, in
         __syncthreads();
         if (grp == 0 && e < per) {
             double tr = 0.0, ti = 0.0;
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 16; ++q) {
                 tr += part[q][el].x;
                 ti += part[q][el].y;
             }
@@ -578,8 +578,8 @@ hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0
                                  const NpfOut *fin)
 {
     const int64_t per = J * p->n;
-    int64_t wg = (per + 31) / 32;
-    if (wg > 4096) wg = 4096;
+    int64_t wg = (per + 15) / 16;
+    if (wg > 8192) wg = 8192;
     hipLaunchKernelGGL(reduce_parts, dim3(unsigned(wg)), dim3(256), 0, s,
                        reinterpret_cast<const double2 *>(ws + p->lay.parts), nparts, p->Jpad, J,
                        p->n, j0, reinterpret_cast<double2 *>(P), reinterpret_cast<double2 *>(psum),

@@ -95,7 +95,7 @@ struct npf_plan_s {
     bool concurrent = false;
     npf::Layout ord[NPF_MAX_ORDER + 1];
     hipStream_t side[NPF_MAX_ORDER + 1] = {};
-    hipEvent_t ev_prep = nullptr, ev_done[NPF_MAX_ORDER + 1] = {};
+    hipEvent_t ev_start = nullptr, ev_prep = nullptr, ev_done[NPF_MAX_ORDER + 1] = {};
     ~npf_plan_s();
 };
 

@@ -132,6 +132,7 @@ npf_plan_s::~npf_plan_s()
     for (auto &e : ev_done)
         if (e) (void)hipEventDestroy(e);
     if (ev_prep) (void)hipEventDestroy(ev_prep);
+    if (ev_start) (void)hipEventDestroy(ev_start);
 }
 
 extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
