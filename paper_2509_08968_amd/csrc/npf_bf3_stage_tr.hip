@@ -9,20 +9,30 @@ constexpr int kThreads = kBf3Threads;
 
 // ------------------------------------------------------------------ one chain stage, n > 64
 // Same arithmetic as stage_bf3; a workgroup owns a range of TT t-tiles (grid.z) and keeps
-// only that slice of the Phi^T planes in LDS.  The gathered rows are loaded one K-chunk
-// ahead (the last chunk of an item prefetches the first chunk of the next item).  With
-// fewer than four 16-mode tiles in the block, the four waves take IPW items per iteration
-// (item slot = wave / (4 / IPW)).
-template <int NP, int SUF, int TT, int IPW>
+// only that slice of the Phi^T planes in LDS.  NW waves: WPI = NW / IPW waves per item (one
+// 16-mode tile each) and IPW items per iteration (item slot = wave / WPI); with eight waves
+// two waves share each SIMD, so that one issues while the other waits.  The gathered rows
+// are loaded PD K-chunks ahead: the chunk PD places later in the sequence of (item, chunk)
+// is loaded into a register slot as soon as that slot's chunk has been split.  Every lane
+// loads every row of its chunks: rows a >= n read the row of a = 0, whose product with the
+// zero rows of the Phi planes adds nothing, and a lane whose next item is absent reloads its
+// current item -- so the loads carry no branches.
+template <int NP, int SUF, int TT, int IPW, int NW>
 __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockPos bp)
 {
     constexpr int KC = NP / 32, TW = TT * 16, AG = NP / 8;
-    constexpr int WPI = 4 / IPW;
+    constexpr int PD = (NW == 8) ? 1 : ((NP == 192) ? 3 : KC);
+    static_assert(KC % PD == 0, "chunk slots must repeat at every item");
+    constexpr int WPI = NW / IPW;
     extern __shared__ __align__(16) char lds[];
-    // Gather tables, three buffers in rotation: iteration k's tables are read in iterations
-    // k-1 (the first chunk) and k (the others) and rewritten in iteration k+2 before that
-    // iteration's barrier, i.e. after every wave has passed the barrier of iteration k+1.
+    // Per iteration, three buffers in rotation: iteration k's tables are read in iterations
+    // k-1 and k and rewritten in iteration k+2 before that iteration's barrier, i.e. after
+    // every wave has passed the barrier of iteration k+1.  sidx: gather rows of each item
+    // slot; sbase: the item's input block and output row offsets; sm: last(p), or -1 for an
+    // absent item.
     __shared__ int32_t sidx[3][IPW][NP];
+    __shared__ int64_t sbase[3][IPW][2];
+    __shared__ int32_t sm[3][IPW];
     __shared__ int64_t rowoff[TW];
     const int t_base = int(bp.z) * TW;
     {
@@ -44,68 +54,83 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
     const int g = lane >> 4, c = lane & 15;
     const int islot = wave / WPI;
     const int64_t jw = (int64_t(bp.y) * WPI + wave % WPI) * 16;
-    const bool wave_on = jw < a.Jpad && islot < IPW;
-    const float2 *X = static_cast<const float2 *>(a.X);
-    const unsigned jp = unsigned(a.Jpad);
+    const bool wave_on = jw < a.Jpad;
+    const float2 *X = static_cast<const float2 *>(a.X) + jw + c;
+    const uint32_t jp = uint32_t(a.Jpad);
     const int nn = int(a.n);
     const int64_t istride = int64_t(bp.gx) * IPW;
 
-    // Gather tables of the items ib .. ib + IPW - 1 into buffer buf.
-    auto build_idx = [&](int64_t ib, int buf) {
-        for (int xq = threadIdx.x; xq < IPW * nn; xq += blockDim.x) {
-            const int q = xq / nn;
+    // Tables of the items ib .. ib + IPW - 1 into buffer buf.
+    auto build = [&](int64_t ib, int buf) {
+        for (int xq = threadIdx.x; xq < IPW * NP; xq += blockDim.x) {
+            const int q = xq / NP;
+            const int x = xq - q * NP;
             const int64_t itq = ib + q;
-            if (itq >= a.items) break;
-            const uint64_t pk = a.stab[itq % a.U_suf];
-            const int32_t x = int32_t(xq - q * nn);
+            if (itq >= a.items) {
+                if (x == 0) sm[buf][q] = -1;
+                continue;
+            }
+            const int64_t rp = itq / a.U_suf, rs = itq - rp * a.U_suf;
+            if (x == 0) {
+                sbase[buf][q][0] = rp * a.U_in * a.Jpad;
+                sbase[buf][q][1] = (rp * a.U_suf + rs) * a.Jpad;
+                sm[buf][q] = (a.i > 1) ? int((a.ptab[rp] >> (8 * (a.i - 2))) & 0xff) : 0;
+            }
+            const uint64_t pk = a.stab[rs];
+            const int32_t xe = (x < nn) ? x : 0;
             int64_t r = 0;
             int qq = 0;
 #pragma unroll
             for (int l = 0; l < SUF; ++l) {
                 const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
-                if (sl <= x) {
+                if (sl <= xe) {
                     r += colex_term_c(sl, l + 1);
                     ++qq;
                 } else {
                     r += colex_term_c(sl, l + 2);
                 }
             }
-            sidx[buf][q][x] = int32_t(r + colex_term_c(x, qq + 1));
+            sidx[buf][q][x] = int32_t(r + colex_term_c(xe, qq + 1));
         }
     };
-    // last(p) of an item, and whether this workgroup's t-range has any t >= last(p).
-    auto item_m = [&](int64_t it) {
-        return (a.i > 1) ? int((a.ptab[it / a.U_suf] >> (8 * (a.i - 2))) & 0xff) : 0;
-    };
-    auto active = [&](int m) { return t_base + TW > m; };
-    auto load_chunk = [&](int64_t it, int buf, int kc, float2 (&dst)[8]) {
-        const float2 *src = X + (it / a.U_suf) * a.U_in * a.Jpad + jw + c;
+    // Whether this workgroup's t-range has any t >= last(p) (never for an absent item).
+    auto active = [&](int m) { return m >= 0 && t_base + TW > m; };
+    auto load_chunk = [&](const float2 *src, const int32_t *rows, int kc, float2 (&dst)[8]) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int ar = kc * 32 + 8 * g + q;
-            dst[q] = ar < nn ? src[uint64_t(unsigned(sidx[buf][islot][ar])) * jp]
-                             : make_float2(0.f, 0.f);
-        }
+        for (int q = 0; q < 8; ++q)
+            dst[q] = src[uint64_t(uint32_t(rows[kc * 32 + 8 * g + q])) * jp];
     };
 
     // ib: the workgroup's first item of the iteration (uniform); it = ib + islot.
     int64_t ib = int64_t(bp.x) * IPW;
     int buf = 0;
-    float2 cur[8];
-    if (ib < a.items) build_idx(ib, 0);
+    float2 ring[PD][8];       // slot kc % PD: chunk kc of the current item, then kc + PD
+    if (ib < a.items) build(ib, 0);
+    else if (threadIdx.x < IPW) sm[0][threadIdx.x] = -1;
     __syncthreads();          // also orders the LDS slice of Phi
-    if (ib + islot < a.items && wave_on && active(item_m(ib + islot))) load_chunk(ib + islot, 0, 0, cur);
+    if (wave_on && active(sm[0][islot])) {
+#pragma unroll
+        for (int kc = 0; kc < PD; ++kc) load_chunk(X + sbase[0][islot][0], sidx[0][islot], kc, ring[kc]);
+    }
     for (; ib < a.items; ib += istride, buf = (buf == 2) ? 0 : buf + 1) {
         const int64_t ibn = ib + istride;
         const int nbuf = (buf == 2) ? 0 : buf + 1;
-        if (ibn < a.items) build_idx(ibn, nbuf);
+        if (ibn < a.items) build(ibn, nbuf);
+        else if (threadIdx.x < IPW) sm[nbuf][threadIdx.x] = -1;
         __syncthreads();
-        const int64_t it = ib + islot, itn = ibn + islot;
-        if (!wave_on || it >= a.items) continue;
-        const int m = item_m(it);
-        const bool next_on = itn < a.items && active(item_m(itn));
+        const int m = sm[buf][islot];
+        if (!wave_on || m < 0) continue;
+        const bool next_on = active(sm[nbuf][islot]);
+        const float2 *src = X + sbase[buf][islot][0];
+        const int32_t *rows = sidx[buf][islot];
+        // The next item's rows, or the current ones again when there is none.
+        const float2 *src_n = next_on ? X + sbase[nbuf][islot][0] : src;
+        const int32_t *rows_n = next_on ? sidx[nbuf][islot] : rows;
         if (!active(m)) {
-            if (next_on) load_chunk(itn, nbuf, 0, cur);
+            if (next_on) {
+#pragma unroll
+                for (int kc = 0; kc < PD; ++kc) load_chunk(src_n, rows_n, kc, ring[kc]);
+            }
             continue;
         }
         const int tt0 = (m > t_base) ? (m - t_base) / 16 : 0;
@@ -117,11 +142,10 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
             for (int tt = 0; tt < TT; ++tt) sr[tt] = si[tt] = srl[tt] = sil[tt] = v4f{0, 0, 0, 0};
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
-                float2 nxt[8];
-                if (kc + 1 < KC) load_chunk(it, buf, kc + 1, nxt);
-                else if (next_on) load_chunk(itn, nbuf, 0, nxt);
                 Split3 xr, xi;
-                split_x(cur, xr, xi);
+                split_x(ring[kc % PD], xr, xi);
+                if (kc + PD < KC) load_chunk(src, rows, kc + PD, ring[kc % PD]);
+                else load_chunk(src_n, rows_n, kc + PD - KC, ring[kc % PD]);
                 const Split3 xng = negx3(xi);
 #pragma unroll
                 for (int tt = T0; tt < TT; ++tt) {
@@ -138,8 +162,6 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
                     mm6s(pr, xi, si[tt], sil[tt]);
                     mm6s(pi, xr, si[tt], sil[tt]);
                 }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
             }
         };
         switch (tt0) {
@@ -148,8 +170,7 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
         case 2: if constexpr (TT > 2) sweep(std::integral_constant<int, (TT > 2 ? 2 : 0)>{}); break;
         default: if constexpr (TT > 3) sweep(std::integral_constant<int, (TT > 3 ? 3 : 0)>{}); break;
         }
-        const int64_t rp = it / a.U_suf, rs = it % a.U_suf;
-        float2 *dst = static_cast<float2 *>(a.out) + (rp * a.U_suf + rs) * a.Jpad + jw + c;
+        float2 *dst = static_cast<float2 *>(a.out) + sbase[buf][islot][1] + jw + c;
 #pragma unroll
         for (int tt = 0; tt < TT; ++tt) {
             if (tt < tt0) continue;
@@ -164,11 +185,11 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
     }
 }
 
-template <int NP, int SUF, int TT, int IPW>
-__global__ void __launch_bounds__(kThreads)
+template <int NP, int SUF, int TT, int IPW, int NW>
+__global__ void __launch_bounds__(NW * 64)
 stage_bf3_tr(Bf3Args a)
 {
-    stage_bf3_tr_body<NP, SUF, TT, IPW>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
+    stage_bf3_tr_body<NP, SUF, TT, IPW, NW>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
 }
 
 // The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
@@ -178,7 +199,7 @@ __global__ void __launch_bounds__(kThreads)
 stage_bf3_tr_multi(const Bf3Args *__restrict__ as, const int32_t *__restrict__ first, int nsys)
 {
     const BlockPos bp = system_block(first, nsys);
-    stage_bf3_tr_body<NP, SUF, TT, IPW>(as[bp.sys], bp);
+    stage_bf3_tr_body<NP, SUF, TT, IPW, 4>(as[bp.sys], bp);
 }
 
 }  // namespace
@@ -189,8 +210,9 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     if (p.npad <= 64) return launch_stage_bf3_small(ca, i);
     const Bf3Args a = stage_args(ca, i);
     const int suf = ca.M - i;
-    const int ipw = bf3_items_per_group(p.Jpad);
-    const int64_t jgroups = (p.Jpad / 16 * ipw + 3) / 4;
+    constexpr int nw = 8;
+    const int ipw = bf3_items_per_group(p.Jpad) * nw / 4;     // items per iteration
+    const int64_t jgroups = (p.Jpad / 16 * ipw + nw - 1) / nw;
     int64_t groups = 512 / jgroups;
     const int64_t need = (a.items + ipw - 1) / ipw;
     if (groups > need) groups = need;
@@ -199,14 +221,15 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     if (p.npad == NP_ && suf == S_ && ipw == IPW_) {                                        \
         const dim3 grid{unsigned(groups), unsigned(jgroups), unsigned((NP_ / 16 + TT_ - 1) / TT_)}; \
         const size_t shm = size_t(12 * NP_ * TT_ * 16);                                     \
-        set_lds_limit(stage_bf3_tr<NP_, S_, TT_, IPW_>, int(shm));                           \
-        hipLaunchKernelGGL((stage_bf3_tr<NP_, S_, TT_, IPW_>), grid, dim3(kThreads), shm, ca.stream, a); \
+        set_lds_limit(stage_bf3_tr<NP_, S_, TT_, IPW_, nw>, int(shm));                       \
+        hipLaunchKernelGGL((stage_bf3_tr<NP_, S_, TT_, IPW_, nw>), grid, dim3(nw * 64), shm,  \
+                           ca.stream, a);                                                    \
         return hipGetLastError();                                                            \
     }
 #define NPF_STAGE_TR_NP(NP_, TT_)                                                     \
-    NPF_STAGE_TR(NP_, 1, TT_, 1) NPF_STAGE_TR(NP_, 2, TT_, 1) NPF_STAGE_TR(NP_, 3, TT_, 1) \
     NPF_STAGE_TR(NP_, 1, TT_, 2) NPF_STAGE_TR(NP_, 2, TT_, 2) NPF_STAGE_TR(NP_, 3, TT_, 2) \
-    NPF_STAGE_TR(NP_, 1, TT_, 4) NPF_STAGE_TR(NP_, 2, TT_, 4) NPF_STAGE_TR(NP_, 3, TT_, 4)
+    NPF_STAGE_TR(NP_, 1, TT_, 4) NPF_STAGE_TR(NP_, 2, TT_, 4) NPF_STAGE_TR(NP_, 3, TT_, 4) \
+    NPF_STAGE_TR(NP_, 1, TT_, 8) NPF_STAGE_TR(NP_, 2, TT_, 8) NPF_STAGE_TR(NP_, 3, TT_, 8)
     NPF_STAGE_TR_NP(96, 3) NPF_STAGE_TR_NP(128, 4) NPF_STAGE_TR_NP(160, 2)
     NPF_STAGE_TR_NP(192, 2) NPF_STAGE_TR_NP(224, 2) NPF_STAGE_TR_NP(256, 2)
 #undef NPF_STAGE_TR_NP
