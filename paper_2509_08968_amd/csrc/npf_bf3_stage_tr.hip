@@ -21,7 +21,7 @@ template <int NP, int SUF, int TT, int IPW, int NW>
 __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockPos bp)
 {
     constexpr int KC = NP / 32, TW = TT * 16, AG = NP / 8;
-    constexpr int PD = (NW == 8) ? 1 : ((NP == 192) ? 3 : KC);
+    constexpr int PD = (NW == 8) ? (KC % 2 == 0 ? 2 : 1) : ((NP == 192) ? 3 : KC);
     static_assert(KC % PD == 0, "chunk slots must repeat at every item");
     constexpr int WPI = NW / IPW;
     extern __shared__ __align__(16) char lds[];
