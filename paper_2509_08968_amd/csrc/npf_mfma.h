@@ -130,9 +130,10 @@ __device__ __forceinline__ void split_pair(float x0, float x1, unsigned &h, unsi
     const unsigned c0 = __float_as_uint(r0), c1 = __float_as_uint(r1);
     const float q0 = r0 - __uint_as_float(c0 & 0xffff0000u);
     const float q1 = r1 - __uint_as_float(c1 & 0xffff0000u);
-    h = (b0 >> 16) | (b1 & 0xffff0000u);
-    m = (c0 >> 16) | (c1 & 0xffff0000u);
-    l = (__float_as_uint(q0) >> 16) | (__float_as_uint(q1) & 0xffff0000u);
+    // v_perm_b32: bytes 2-3 of the second operand, then bytes 2-3 of the first.
+    h = __builtin_amdgcn_perm(b1, b0, 0x07060302u);
+    m = __builtin_amdgcn_perm(c1, c0, 0x07060302u);
+    l = __builtin_amdgcn_perm(__float_as_uint(q1), __float_as_uint(q0), 0x07060302u);
 }
 
 // Split eight FP32 values into the three BF16 operand vectors.
