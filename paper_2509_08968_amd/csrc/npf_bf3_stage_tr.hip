@@ -230,8 +230,10 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     NPF_STAGE_TR(NP_, 1, TT_, 2) NPF_STAGE_TR(NP_, 2, TT_, 2) NPF_STAGE_TR(NP_, 3, TT_, 2) \
     NPF_STAGE_TR(NP_, 1, TT_, 4) NPF_STAGE_TR(NP_, 2, TT_, 4) NPF_STAGE_TR(NP_, 3, TT_, 4) \
     NPF_STAGE_TR(NP_, 1, TT_, 8) NPF_STAGE_TR(NP_, 2, TT_, 8) NPF_STAGE_TR(NP_, 3, TT_, 8)
-    NPF_STAGE_TR_NP(96, 3) NPF_STAGE_TR_NP(128, 4) NPF_STAGE_TR_NP(160, 2)
-    NPF_STAGE_TR_NP(192, 2) NPF_STAGE_TR_NP(224, 2) NPF_STAGE_TR_NP(256, 2)
+    // Three t-tiles per slice where the slice still fits LDS beside the largest tables: fewer
+    // slices, fewer gathers of the same rows.
+    NPF_STAGE_TR_NP(96, 3) NPF_STAGE_TR_NP(128, 4) NPF_STAGE_TR_NP(160, 3)
+    NPF_STAGE_TR_NP(192, 3) NPF_STAGE_TR_NP(224, 3) NPF_STAGE_TR_NP(256, 2)
 #undef NPF_STAGE_TR_NP
 #undef NPF_STAGE_TR
     return hipErrorInvalidValue;
