@@ -250,9 +250,12 @@ bool ensure_streams(npf_plan_t plan)
     return hipEventCreateWithFlags(&plan->ev_prep, hipEventDisableTiming) == hipSuccess;
 }
 
-// Graph cache: one instantiated graph per distinct argument set (problem, descriptors,
-// pointers, stream), least recently used evicted.
+// Graph cache: one instantiated graph per distinct argument set (plan, problem,
+// descriptors, pointers, stream), least recently used evicted.  A graph captured from a
+// concurrent plan holds that plan's side streams and events, so a plan's graphs are
+// destroyed with the plan (drop_plan_graphs), never after it.
 struct GraphKey {
+    const void *plan;
     npf_problem prob;
     npf_tensor A[NPF_MAX_ORDER];
     const void *ptr[7];
@@ -273,6 +276,21 @@ uint64_t g_graph_clock = 0;
 constexpr size_t kMaxGraphs = 8;
 
 }  // namespace
+
+namespace npf {
+void drop_plan_graphs(const npf_plan_s *plan)
+{
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (size_t i = 0; i < g_graphs.size();) {
+        if (g_graphs[i].key.plan == plan) {
+            (void)hipGraphExecDestroy(g_graphs[i].exec);
+            g_graphs.erase(g_graphs.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+}  // namespace npf
 
 extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
                        const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
@@ -295,6 +313,7 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
 
     GraphKey key;
     std::memset(&key, 0, sizeof(key));
+    key.plan = plan;
     key.prob = plan->prob;
     for (int M = 2; M <= plan->N; ++M) key.A[M - 2] = A[M - 2];
     const void *ptrs[7] = {U, V, lambda, ws, P_out, npf_out, reinterpret_cast<const void *>(ws_bytes)};

@@ -210,6 +210,8 @@ hipError_t launch_fused_bf3_tr_multi(int npad, int M, const MultiLaunch &m);
 hipError_t launch_stage_bf3_multi(int npad, int suf, const MultiLaunch &m);
 hipError_t launch_stage_bf3_tr_multi(int npad, int suf, const MultiLaunch &m);
 int fused_bf3_tr_kranges(int64_t npad);
+// Destroys the graphs npf_run instantiated for a plan (npf_plan_destroy).
+void drop_plan_graphs(const npf_plan_s *plan);
 int stage_bf3_tr_tiles(int64_t npad);
 // Partial sums of a block's fused-kernel slots (nparts of them) into P rows and psum.
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,

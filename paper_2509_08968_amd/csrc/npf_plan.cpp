@@ -224,7 +224,12 @@ extern "C" int npf_plan_info(npf_plan_t plan, npf_plan_report *r)
     return NPF_OK;
 }
 
-extern "C" void npf_plan_destroy(npf_plan_t plan) { delete plan; }
+extern "C" void npf_plan_destroy(npf_plan_t plan)
+{
+    if (!plan) return;
+    drop_plan_graphs(plan);     // before the side streams and events the graphs were made from
+    delete plan;
+}
 
 // Alg. 1 steps 1-15: the full tensor has n_dim dimensions of extent n_s; while its size
 // exceeds the limit, drop the outermost dimension and either batch it one index at a time

@@ -152,6 +152,33 @@ def test_graph_replay_matches_eager(torch_dev):
     assert torch.allclose(Pg, 2.0 * ref_P, rtol=1e-5, atol=0)
 
 
+def test_many_plans_graphs_released_with_plan(torch_dev):
+    """More concurrent-order plans than npf_run keeps graphs for, one after another: each is
+    captured, replayed, checked bitwise against an eager run and destroyed.  A plan's graphs
+    are released with the plan (before its side streams and events), so later captures and
+    evictions never touch a destroyed plan's graph."""
+    torch, dev = torch_dev
+    st = torch.cuda.Stream()
+    for q in range(12):
+        n = 20 + 2 * q
+        s = I.block_sparse_system(n, [2, 3], 3600 + q)
+        print(f"[many plans] q={q} n={n}", flush=True)
+        d = B.upload_system(s, dev)
+        pe = B.Plan(n, 3, "bf16x3", s.eps, s.tau, s.delta, graph=False)
+        pg = B.Plan(n, 3, "bf16x3", s.eps, s.tau, s.delta, graph=True)
+        ws_e, ws_g = pe.workspace(dev), pg.workspace(dev)
+        Pe = torch.empty((2, n, n), dtype=torch.complex128, device=dev)
+        Ne = torch.empty((n, n), dtype=torch.complex128, device=dev)
+        Pg, Ng = torch.empty_like(Pe), torch.empty_like(Ne)
+        pe.run(d.tensors, d.U, d.V, d.lam, ws_e, Pe, Ne, st)
+        for _ in range(2):
+            pg.run(d.tensors, d.U, d.V, d.lam, ws_g, Pg, Ng, st)
+        torch.cuda.synchronize()
+        assert torch.equal(Pg, Pe) and torch.equal(Ng, Ne), q
+        pg.close()
+        pe.close()
+
+
 @pytest.fixture(scope="module")
 def dense128():
     """n=128, orders 2-4 dense with planted resonances and the oracle's P rows for two
