@@ -352,7 +352,9 @@ extern "C" int npf_batch_create(const npf_problem *problems, int64_t count, int6
                         const double Jn = double(p->Jpad) * double(p->n);
                         const double Jf = double(p->n) * double(p->n);
                         if (L.kind == 0) {
-                            L.cap.push_back(std::max<int64_t>(1, p->U[i - 1] * p->U[M - i]));
+                            // The t-range stage takes two items per workgroup iteration.
+                            const int64_t items = p->U[i - 1] * p->U[M - i];
+                            L.cap.push_back(std::max<int64_t>(1, npad > 64 ? (items + 1) / 2 : items));
                             L.work.push_back(Jn * double(p->U[i]) * double(p->U[M - i]));
                             L.flops += 8.0 * Jf * double(p->U[i]) * double(p->U[M - i]);
                         } else {

@@ -195,11 +195,11 @@ stage_bf3_tr(Bf3Args a)
 // The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
 // run system s with the arguments as[s].
 template <int NP, int SUF, int TT, int IPW>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(512)
 stage_bf3_tr_multi(const Bf3Args *__restrict__ as, const int32_t *__restrict__ first, int nsys)
 {
     const BlockPos bp = system_block(first, nsys);
-    stage_bf3_tr_body<NP, SUF, TT, IPW, 4>(as[bp.sys], bp);
+    stage_bf3_tr_body<NP, SUF, TT, IPW, 8>(as[bp.sys], bp);
 }
 
 }  // namespace
@@ -239,8 +239,9 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     return hipErrorInvalidValue;
 }
 
-// t-tiles per workgroup of the t-range stage kernel for a system of npad states.
-int stage_bf3_tr_tiles(int64_t npad) { return npad == 96 ? 3 : (npad == 128 ? 4 : 2); }
+// t-tiles per workgroup of the t-range stage kernel for a system of npad states (as in
+// launch_stage_bf3).
+int stage_bf3_tr_tiles(int64_t npad) { return npad == 128 ? 4 : (npad == 256 ? 2 : 3); }
 
 hipError_t launch_stage_bf3_tr_multi(int npad, int suf, const MultiLaunch &m)
 {
@@ -248,17 +249,18 @@ hipError_t launch_stage_bf3_tr_multi(int npad, int suf, const MultiLaunch &m)
     const dim3 grid{unsigned(m.groups), unsigned(m.gy), unsigned((npad / 16 + tt - 1) / tt)};
     const size_t shm = size_t(12 * npad * tt * 16);
     const Bf3Args *as = static_cast<const Bf3Args *>(m.args);
+    // Eight waves: two items of up to 64 modes per iteration.
 #define NPF_STAGE_TR_MULTI(NP_, S_, TT_)                                                       \
     if (npad == NP_ && suf == S_) {                                                           \
-        set_lds_limit(stage_bf3_tr_multi<NP_, S_, TT_, 1>, int(shm));                          \
-        hipLaunchKernelGGL((stage_bf3_tr_multi<NP_, S_, TT_, 1>), grid, dim3(kThreads), shm,   \
+        set_lds_limit(stage_bf3_tr_multi<NP_, S_, TT_, 2>, int(shm));                          \
+        hipLaunchKernelGGL((stage_bf3_tr_multi<NP_, S_, TT_, 2>), grid, dim3(512), shm,        \
                            m.stream, as, m.first, m.nsys);                                     \
         return hipGetLastError();                                                              \
     }
 #define NPF_STAGE_TR_MULTI_NP(NP_, TT_) \
     NPF_STAGE_TR_MULTI(NP_, 1, TT_) NPF_STAGE_TR_MULTI(NP_, 2, TT_) NPF_STAGE_TR_MULTI(NP_, 3, TT_)
-    NPF_STAGE_TR_MULTI_NP(96, 3) NPF_STAGE_TR_MULTI_NP(128, 4) NPF_STAGE_TR_MULTI_NP(160, 2)
-    NPF_STAGE_TR_MULTI_NP(192, 2) NPF_STAGE_TR_MULTI_NP(224, 2) NPF_STAGE_TR_MULTI_NP(256, 2)
+    NPF_STAGE_TR_MULTI_NP(96, 3) NPF_STAGE_TR_MULTI_NP(128, 4) NPF_STAGE_TR_MULTI_NP(160, 3)
+    NPF_STAGE_TR_MULTI_NP(192, 3) NPF_STAGE_TR_MULTI_NP(224, 3) NPF_STAGE_TR_MULTI_NP(256, 2)
 #undef NPF_STAGE_TR_MULTI_NP
 #undef NPF_STAGE_TR_MULTI
     return hipErrorInvalidValue;
