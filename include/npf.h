@@ -128,8 +128,8 @@ typedef struct npf_plan_report {
  * workspace size.  Returns NPF_E_BUDGET if even the smallest block does not fit. */
 int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out);
 int npf_plan_info(npf_plan_t plan, npf_plan_report *report);
-/* Releases the plan and the graphs npf_run instantiated for it.  No run of the plan may
- * still be executing (synchronise its streams first). */
+/* Releases the plan (host metadata only: runs already enqueued are unaffected, and the
+ * graphs npf_run instantiated stay cached for later plans of the same problem). */
 void npf_plan_destroy(npf_plan_t plan);
 
 /* Alg. 2 steps 1-4 for output-mode block `block` (modes [block*J, min(n, block*J+J)))

@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, block loops and kernel sequencing.
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -234,28 +235,24 @@ extern "C" int npf_hash_fill(int64_t n, int32_t order, uint64_t seed, double sca
 namespace {
 
 // The launch sequence of npf_run (eager).
+struct SideSet;
 int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
               const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s,
-              bool concurrent = false);
+              const SideSet *cs = nullptr);
 
-// Side streams and events of a concurrent plan (made once, before the first capture).
-bool ensure_streams(npf_plan_t plan)
-{
-    if (plan->ev_prep) return true;
-    for (int M = 1; M < plan->N; ++M)       // side[1]: operand staging; side[M]: order M
-        if (hipStreamCreateWithFlags(&plan->side[M], hipStreamNonBlocking) != hipSuccess) return false;
-    for (int M = 2; M <= plan->N; ++M)
-        if (hipEventCreateWithFlags(&plan->ev_done[M], hipEventDisableTiming) != hipSuccess) return false;
-    if (hipEventCreateWithFlags(&plan->ev_start, hipEventDisableTiming) != hipSuccess) return false;
-    return hipEventCreateWithFlags(&plan->ev_prep, hipEventDisableTiming) == hipSuccess;
-}
+// Side streams and events of the concurrent captures: one set per device, made on the
+// first concurrent capture and kept for the life of the process, since the cached graphs
+// captured from them outlive the plans.  Used only while capturing, under g_graph_mu.
+struct SideSet {
+    hipStream_t side[NPF_MAX_ORDER + 1] = {};   // side[1]: operand staging; side[M]: order M
+    hipEvent_t ev_start = nullptr, ev_prep = nullptr, ev_done[NPF_MAX_ORDER + 1] = {};
+    bool ok = false;
+};
 
-// Graph cache: one instantiated graph per distinct argument set (plan, problem,
-// descriptors, pointers, stream), least recently used evicted.  A graph captured from a
-// concurrent plan holds that plan's side streams and events, so a plan's graphs are
-// destroyed with the plan (drop_plan_graphs), never after it.
+// Graph cache: one instantiated graph per distinct argument set (problem, descriptors,
+// pointers, stream), at most kMaxGraphs of them.  A plan is host metadata only: a later
+// plan of the same problem replays the graph (the launches are a function of the key).
 struct GraphKey {
-    const void *plan;
     npf_problem prob;
     npf_tensor A[NPF_MAX_ORDER];
     const void *ptr[7];
@@ -273,24 +270,31 @@ struct GraphEntry {
 std::mutex g_graph_mu;
 std::vector<GraphEntry> g_graphs;
 uint64_t g_graph_clock = 0;
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxGraphs = 16;
+std::map<int, SideSet> g_side;
+
+// The current device's side set (made on first use), or null if it cannot be made.
+const SideSet *side_set()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    SideSet &S = g_side[dev];
+    if (S.ok) return &S;
+    for (int M = 1; M < NPF_MAX_ORDER; ++M)
+        if (!S.side[M] && hipStreamCreateWithFlags(&S.side[M], hipStreamNonBlocking) != hipSuccess)
+            return nullptr;
+    for (int M = 2; M <= NPF_MAX_ORDER; ++M)
+        if (!S.ev_done[M] && hipEventCreateWithFlags(&S.ev_done[M], hipEventDisableTiming) != hipSuccess)
+            return nullptr;
+    if (!S.ev_start && hipEventCreateWithFlags(&S.ev_start, hipEventDisableTiming) != hipSuccess)
+        return nullptr;
+    if (!S.ev_prep && hipEventCreateWithFlags(&S.ev_prep, hipEventDisableTiming) != hipSuccess)
+        return nullptr;
+    S.ok = true;
+    return &S;
+}
 
 }  // namespace
-
-namespace npf {
-void drop_plan_graphs(const npf_plan_s *plan)
-{
-    std::lock_guard<std::mutex> lock(g_graph_mu);
-    for (size_t i = 0; i < g_graphs.size();) {
-        if (g_graphs[i].key.plan == plan) {
-            (void)hipGraphExecDestroy(g_graphs[i].exec);
-            g_graphs.erase(g_graphs.begin() + i);
-        } else {
-            ++i;
-        }
-    }
-}
-}  // namespace npf
 
 extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
                        const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
@@ -313,7 +317,6 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
 
     GraphKey key;
     std::memset(&key, 0, sizeof(key));
-    key.plan = plan;
     key.prob = plan->prob;
     for (int M = 2; M <= plan->N; ++M) key.A[M - 2] = A[M - 2];
     const void *ptrs[7] = {U, V, lambda, ws, P_out, npf_out, reinterpret_cast<const void *>(ws_bytes)};
@@ -325,10 +328,13 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
             e.used = ++g_graph_clock;
             return check_hip(hipGraphLaunch(e.exec, s), "graph launch");
         }
-    const bool conc = plan->concurrent && ensure_streams(plan);
+    // A full cache runs new argument sets eagerly: cached graphs are not destroyed while the
+    // process runs (a host fault was seen when evicting them under many distinct problems).
+    if (g_graphs.size() >= kMaxGraphs) return run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
+    const SideSet *cs = plan->concurrent ? side_set() : nullptr;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
-    rc = run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s, conc);
+    rc = run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s, cs);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
     if (rc != NPF_OK) {
@@ -340,13 +346,6 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
     const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) return check_hip(ei, "graph instantiate");
-    if (g_graphs.size() >= kMaxGraphs) {
-        size_t lru = 0;
-        for (size_t i = 1; i < g_graphs.size(); ++i)
-            if (g_graphs[i].used < g_graphs[lru].used) lru = i;
-        (void)hipGraphExecDestroy(g_graphs[lru].exec);
-        g_graphs.erase(g_graphs.begin() + lru);
-    }
     g_graphs.push_back({key, exec, ++g_graph_clock});
     return check_hip(hipGraphLaunch(exec, s), "graph launch");
 }
@@ -355,8 +354,9 @@ namespace {
 
 int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
               const void *lambda, void *ws, void *P_out, void *npf_out, hipStream_t s,
-              bool concurrent)
+              const SideSet *cs)
 {
+    const bool concurrent = cs != nullptr;
     // Concurrent (captured runs of single-block plans with several orders): the operands are
     // staged on side stream 1 while every order starts its upper-index contraction; order
     // M < N runs its chain and last stage on side stream M; the partial sums of every order
@@ -365,10 +365,10 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
     char *w = static_cast<char *>(ws);
     const int64_t nn = plan->n * plan->n;
     if (concurrent) {
-        rc = check_hip(hipEventRecord(plan->ev_start, s), "fork");
-        if (!rc) rc = check_hip(hipStreamWaitEvent(plan->side[1], plan->ev_start, 0), "fork");
-        if (!rc) rc = stage_operands(plan, U, V, ws, plan->side[1]);
-        if (!rc) rc = check_hip(hipEventRecord(plan->ev_prep, plan->side[1]), "fork");
+        rc = check_hip(hipEventRecord(cs->ev_start, s), "fork");
+        if (!rc) rc = check_hip(hipStreamWaitEvent(cs->side[1], cs->ev_start, 0), "fork");
+        if (!rc) rc = stage_operands(plan, U, V, ws, cs->side[1]);
+        if (!rc) rc = check_hip(hipEventRecord(cs->ev_prep, cs->side[1]), "fork");
     } else {
         rc = stage_operands(plan, U, V, ws, s);
     }
@@ -387,17 +387,17 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
     };
     for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
         const bool on_side = concurrent && M < plan->N;
-        const hipStream_t sm = on_side ? plan->side[M] : s;
-        if (on_side && (rc = check_hip(hipStreamWaitEvent(sm, plan->ev_start, 0), "fork"))) break;
+        const hipStream_t sm = on_side ? cs->side[M] : s;
+        if (on_side && (rc = check_hip(hipStreamWaitEvent(sm, cs->ev_start, 0), "fork"))) break;
         const OrderLayout ol(plan, M);
         const bool tucker = tucker_supported(plan, &A[M - 2], M);
-        if (tucker && concurrent) rc = check_hip(hipStreamWaitEvent(sm, plan->ev_prep, 0), "join");
+        if (tucker && concurrent) rc = check_hip(hipStreamWaitEvent(sm, cs->ev_prep, 0), "join");
         if (!rc && tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, sm);
         for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
             int64_t j0, J;
             block_modes(plan, b, j0, J);
             rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, sm, tucker,
-                           (concurrent && !tucker) ? plan->ev_prep : nullptr);
+                           (concurrent && !tucker) ? cs->ev_prep : nullptr);
             if (rc) break;
             {
                 Timed t(plan, kname(M, "fused"), sm);
@@ -407,11 +407,11 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
             }
             if (!rc && !concurrent) rc = reduce(M, j0, J, s);
         }
-        if (!rc && concurrent) rc = check_hip(hipEventRecord(plan->ev_done[M], sm), "join");
+        if (!rc && concurrent) rc = check_hip(hipEventRecord(cs->ev_done[M], sm), "join");
     }
     if (concurrent)
         for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
-            rc = check_hip(hipStreamWaitEvent(s, plan->ev_done[M], 0), "join");
+            rc = check_hip(hipStreamWaitEvent(s, cs->ev_done[M], 0), "join");
             if (!rc) rc = reduce(M, 0, plan->n, s);
         }
     return rc;

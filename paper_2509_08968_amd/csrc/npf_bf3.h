@@ -40,6 +40,15 @@ struct BlockPos {
     int sys;
 };
 
+// Position along the items of workgroup b of a single-system launch of g workgroups: the
+// workgroups are dealt to the eight XCDs in turn (b % 8), so with g a multiple of 8 each
+// XCD is given a contiguous run of g / 8 starting items -- items that read common rows
+// then meet in the same L2.
+__device__ __forceinline__ int64_t xcd_block(unsigned b, unsigned g)
+{
+    return (g % 8u == 0u) ? int64_t(b % 8u) * (g / 8u) + b / 8u : int64_t(b);
+}
+
 // For a launch over several systems: system s owns workgroups [first[s], first[s+1]) of
 // grid.x (every system at least one).
 __device__ __forceinline__ BlockPos system_block(const int32_t *__restrict__ first, int nsys)

@@ -123,7 +123,7 @@ template <int NP, int SUF>
 __global__ void __launch_bounds__(kThreads, 2)
 stage_bf3(Bf3Args a)
 {
-    stage_bf3_body<NP, SUF>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
+    stage_bf3_body<NP, SUF>(a, BlockPos{xcd_block(blockIdx.x, gridDim.x), gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
 }
 
 // The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
@@ -146,6 +146,7 @@ hipError_t launch_stage_bf3_small(const ChainArgs &ca, int i)
     const int64_t jgroups = (p.Jpad + 63) / 64;
     int64_t groups = 512 / jgroups;
     if (groups > a.items) groups = a.items;
+    if (groups >= 64) groups -= groups % 8;       // whole XCD rounds (xcd_block)
     if (groups < 1) groups = 1;
     const dim3 grid{unsigned(groups), unsigned(jgroups), 1u};
     const size_t shm = size_t(12 * p.npad * p.npad);

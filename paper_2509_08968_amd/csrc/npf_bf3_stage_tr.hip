@@ -189,7 +189,8 @@ template <int NP, int SUF, int TT, int IPW, int NW>
 __global__ void __launch_bounds__(NW * 64)
 stage_bf3_tr(Bf3Args a)
 {
-    stage_bf3_tr_body<NP, SUF, TT, IPW, NW>(a, BlockPos{blockIdx.x, gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
+    stage_bf3_tr_body<NP, SUF, TT, IPW, NW>(
+        a, BlockPos{xcd_block(blockIdx.x, gridDim.x), gridDim.x, int(blockIdx.y), int(blockIdx.z), 0});
 }
 
 // The same for several systems in one launch: workgroups [first[s], first[s+1]) of grid.x
@@ -216,6 +217,7 @@ hipError_t launch_stage_bf3(const ChainArgs &ca, int i)
     int64_t groups = 512 / jgroups;
     const int64_t need = (a.items + ipw - 1) / ipw;
     if (groups > need) groups = need;
+    if (groups >= 64) groups -= groups % 8;       // whole XCD rounds (xcd_block)
     if (groups < 1) groups = 1;
 #define NPF_STAGE_TR(NP_, S_, TT_, IPW_)                                                    \
     if (p.npad == NP_ && suf == S_ && ipw == IPW_) {                                        \

@@ -91,12 +91,10 @@ struct npf_plan_s {
     npf::Profiler prof;
     // Concurrent orders: each order's chain buffers, partials, P scratch and per-row tables
     // in workspace of its own (ord[M]); the shared parts (tuple tables, operands, psum) are
-    // common.  Side streams and events are made on the first captured run.
+    // common.  The side streams and events of the concurrent capture belong to the library
+    // (one set per device), not to the plan.
     bool concurrent = false;
     npf::Layout ord[NPF_MAX_ORDER + 1];
-    hipStream_t side[NPF_MAX_ORDER + 1] = {};
-    hipEvent_t ev_start = nullptr, ev_prep = nullptr, ev_done[NPF_MAX_ORDER + 1] = {};
-    ~npf_plan_s();
 };
 
 namespace npf {
@@ -210,8 +208,6 @@ hipError_t launch_fused_bf3_tr_multi(int npad, int M, const MultiLaunch &m);
 hipError_t launch_stage_bf3_multi(int npad, int suf, const MultiLaunch &m);
 hipError_t launch_stage_bf3_tr_multi(int npad, int suf, const MultiLaunch &m);
 int fused_bf3_tr_kranges(int64_t npad);
-// Destroys the graphs npf_run instantiated for a plan (npf_plan_destroy).
-void drop_plan_graphs(const npf_plan_s *plan);
 int stage_bf3_tr_tiles(int64_t npad);
 // Partial sums of a block's fused-kernel slots (nparts of them) into P rows and psum.
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,

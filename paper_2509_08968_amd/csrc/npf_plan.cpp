@@ -125,16 +125,6 @@ static Layout make_split_layout(const npf_plan_s &p, int64_t Jpad, Layout *ord)
 
 using namespace npf;
 
-npf_plan_s::~npf_plan_s()
-{
-    for (auto &st : side)
-        if (st) (void)hipStreamDestroy(st);
-    for (auto &e : ev_done)
-        if (e) (void)hipEventDestroy(e);
-    if (ev_prep) (void)hipEventDestroy(ev_prep);
-    if (ev_start) (void)hipEventDestroy(ev_start);
-}
-
 extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
 {
     if (!problem || !plan_out) return fail(NPF_E_INVALID, "npf_plan_create: null argument");
@@ -224,12 +214,7 @@ extern "C" int npf_plan_info(npf_plan_t plan, npf_plan_report *r)
     return NPF_OK;
 }
 
-extern "C" void npf_plan_destroy(npf_plan_t plan)
-{
-    if (!plan) return;
-    drop_plan_graphs(plan);     // before the side streams and events the graphs were made from
-    delete plan;
-}
+extern "C" void npf_plan_destroy(npf_plan_t plan) { delete plan; }
 
 // Alg. 1 steps 1-15: the full tensor has n_dim dimensions of extent n_s; while its size
 // exceeds the limit, drop the outermost dimension and either batch it one index at a time
