@@ -89,24 +89,36 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
 #pragma unroll
         for (int kk = 0; kk < KTW; ++kk) rr[kk] = ri[kk] = rrl[kk] = ril[kk] = v4f{0, 0, 0, 0};
 
-        for (int tc = m / 32; tc < KC; ++tc) {
-            const int t0 = tc * 32, tb = t0 + 16 * half;
-            // First product for this wave's 16-row tile (skipped when all its t < last(p)).
-            v4f sr = v4f{0, 0, 0, 0}, si = sr, srl = sr, sil = sr;
-            if (wave_on && tb + 16 > m) {
+        // First product for this wave's 16-row tile of every 32-row chunk tc (skipped when
+        // all its t < last(p)), each K-chunk of the rows split once.
+        const int tc0 = m / 32;
+        v4f sra[KC], sia[KC], srla[KC], sila[KC];
 #pragma unroll
-                for (int kc = 0; kc < KC; ++kc) {
-                    Split3 xr, xi;
-                    split_x(xv[kc], xr, xi);
-                    const Split3 xng = negx3(xi);
+        for (int tc = 0; tc < KC; ++tc) sra[tc] = sia[tc] = srla[tc] = sila[tc] = v4f{0, 0, 0, 0};
+        if (wave_on) {
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                Split3 xr, xi;
+                split_x(xv[kc], xr, xi);
+                const Split3 xng = negx3(xi);
+#pragma unroll
+                for (int tc = 0; tc < KC; ++tc) {
+                    const int tb = tc * 32 + 16 * half;
+                    if (tc < tc0 || tb + 16 <= m) continue;
                     Split3 pr, pi;
                     phi_frags<NP>(Lphi, kc * 32, tb + c, g, pr, pi);
-                    mm6s(pr, xr, sr, srl);
-                    mm6s(pi, xng, sr, srl);
-                    mm6s(pr, xi, si, sil);
-                    mm6s(pi, xr, si, sil);
+                    mm6s(pr, xr, sra[tc], srla[tc]);
+                    mm6s(pi, xng, sra[tc], srla[tc]);
+                    mm6s(pr, xi, sia[tc], sila[tc]);
+                    mm6s(pi, xr, sia[tc], sila[tc]);
                 }
             }
+        }
+#pragma unroll
+        for (int tc = 0; tc < KC; ++tc) {
+            if (tc < tc0) continue;         // uniform: m is the workgroup's
+            const int t0 = tc * 32, tb = t0 + 16 * half;
+            const v4f sr = sra[tc], si = sia[tc], srl = srla[tc], sil = sila[tc];
             // Divisor and division (FP64 divisor) for the tile's rows t = tb + 4g + r.
             // exchange layout [buf][jt][half][r][lane]: lane-contiguous, no bank conflicts
             float2 *xo = Lx + ((buf * 4 + jt) * 2 + half) * 4 * 64 + lane;
