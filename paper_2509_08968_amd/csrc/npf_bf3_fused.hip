@@ -49,22 +49,27 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
         for (int r = 0; r < 4; ++r) pacc_r[kk][r] = pacc_i[kk][r] = 0.0;
 
     const float2 *X = static_cast<const float2 *>(a.X);
+    // The item's rows in FP32 (rows a >= n read row n - 1: the Phi planes are zero there).
+    // The next item's prefix is loaded when an item starts, its rows once the item's first
+    // products have split the current ones.
+    float2 xv[KC][8];
+    auto load_rows = [&](int64_t it) {
+        const float2 *Xp = X + it * a.n * a.Jpad + jw + c;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) xv[kc][s] = Xp[min(kc * 32 + 8 * g + s, nn - 1) * jp];
+    };
     int buf = 0;
+    uint64_t pk = 0, pkn = 0;
+    if (int64_t(bp.x) < a.items) {
+        pk = a.ptab[bp.x];
+        if (wave_on) load_rows(bp.x);
+    }
     // Items are the same for all eight waves (the barriers below are workgroup-uniform).
-    for (int64_t it = bp.x; it < a.items; it += bp.gx) {
-        const uint64_t pk = a.ptab[it];
-        // The item's rows stay in FP32 (split per chunk of the first product when used).
-        float2 xv[KC][8];
-        {
-            const float2 *Xp = X + it * a.n * a.Jpad + jw + c;
-#pragma unroll
-            for (int kc = 0; kc < KC; ++kc)
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int ar = kc * 32 + 8 * g + s;
-                    xv[kc][s] = (wave_on && ar < nn) ? Xp[ar * jp] : make_float2(0.f, 0.f);
-                }
-        }
+    for (int64_t it = bp.x; it < a.items; it += bp.gx, pk = pkn) {
+        const int64_t itn = it + bp.gx;
+        pkn = (itn < a.items) ? a.ptab[itn] : 0;
         int32_t p[M - 1];
 #pragma unroll
         for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
@@ -113,6 +118,7 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
                     mm6s(pi, xr, sia[tc], sila[tc]);
                 }
             }
+            if (itn < a.items) load_rows(itn);
         }
 #pragma unroll
         for (int tc = 0; tc < KC; ++tc) {
