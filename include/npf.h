@@ -100,7 +100,8 @@ typedef struct npf_problem {
 } npf_problem;
 
 /* npf_run replays a HIP graph of its launch sequence when called again with the same
- * problem, pointers, descriptors and stream (the graph is captured on the first call).
+ * problem, pointers, descriptors and stream (the graph is captured on the first call; up to
+ * 16 argument sets are kept for the life of the process, further ones run eagerly).
  * This flag disables that and always launches eagerly.  Graphs are never used on the
  * NULL stream, on a stream that is already capturing, or while profiling. */
 #define NPF_FLAG_NO_GRAPH 1

@@ -33,7 +33,12 @@ def launch_names(workload: str, precision: str, budget: int = 0):
     s = I.WORKLOADS[workload]()
     plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
                   support_max=s.support_max)
+    # Graph replays of single-block plans with several orders run the orders concurrently;
+    # their dispatch order is the capture order: every order's launches, then the partial
+    # sums of every order (the workloads here fit the per-order workspace of that mode).
+    concurrent = plan.n_blocks == 1 and s.order_max >= 3
     names = ["prepare"]
+    reduces = []
     for M in range(2, s.order_max + 1):
         sparse = s.support.get(M) is not None and M not in s.hashed
         tucker = sparse and 1 <= s.support_max <= 8 and (
@@ -50,9 +55,10 @@ def launch_names(workload: str, precision: str, budget: int = 0):
                 names.append(f"o{M}_psi_a")
             if not tucker:
                 names += [f"o{M}_stage{i}" for i in range(1, M)]
-            names += [f"o{M}_fused", f"o{M}_reduce"]
+            names.append(f"o{M}_fused")
+            (reduces if concurrent else names).append(f"o{M}_reduce")
     plan.close()
-    return names
+    return names + reduces
 
 
 def _dispatches(path):
