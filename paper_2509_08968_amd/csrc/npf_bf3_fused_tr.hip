@@ -338,7 +338,7 @@ hipError_t launch_fused_bf3_tr(const npf_plan_s *p, int M, int64_t j0, int64_t J
     const size_t shm = size_t(12 * NP * 32 + 12 * 32 * (NP / ks) + 16 * NP + 4 * 16 * 64 * 4);
 #define NPF_FUSED_TR(NP_, M_, IPW_)                                                             \
     if (NP == NP_ && M == M_ && ipw == IPW_) {                                                 \
-        constexpr int KS_ = NP_ > 224 ? 4 : (NP_ > 128 ? 2 : 1);                               \
+        constexpr int KS_ = NP_ > 224 ? 4 : (NP_ > 160 ? 2 : 1);                               \
         set_lds_limit(fused_bf3_tr<NP_, M_, IPW_, KS_>, int(shm));                             \
         hipLaunchKernelGGL((fused_bf3_tr<NP_, M_, IPW_, KS_>), grid, dim3(512), shm, s, a);    \
         return hipGetLastError();                                                               \
@@ -360,7 +360,7 @@ bool bf3_tr_fused_supported(const npf_plan_s *p)
 }
 
 // State ranges of the reduction for a system of npad states.
-int fused_bf3_tr_kranges(int64_t npad) { return npad > 224 ? 4 : (npad > 128 ? 2 : 1); }
+int fused_bf3_tr_kranges(int64_t npad) { return npad > 224 ? 4 : (npad > 160 ? 2 : 1); }
 
 hipError_t launch_fused_bf3_tr_multi(int npad, int M, const MultiLaunch &m)
 {
@@ -370,7 +370,7 @@ hipError_t launch_fused_bf3_tr_multi(int npad, int M, const MultiLaunch &m)
     const Bf3Args *as = static_cast<const Bf3Args *>(m.args);
 #define NPF_FUSED_TR_MULTI(NP_, M_)                                                          \
     if (npad == NP_ && M == M_) {                                                           \
-        constexpr int KS_ = NP_ > 224 ? 4 : (NP_ > 128 ? 2 : 1);                             \
+        constexpr int KS_ = NP_ > 224 ? 4 : (NP_ > 160 ? 2 : 1);                             \
         set_lds_limit(fused_bf3_tr_multi<NP_, M_, 1, KS_>, int(shm));                         \
         hipLaunchKernelGGL((fused_bf3_tr_multi<NP_, M_, 1, KS_>), grid, dim3(512), shm,      \
                            m.stream, as, m.first, m.nsys);                                   \
