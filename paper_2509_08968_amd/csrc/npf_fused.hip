@@ -414,10 +414,17 @@ reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, in
         if (e < per) {
             const int64_t j = e / n, k = e % n;
             const int64_t b1 = (grp + 1) * chunk < nparts ? (grp + 1) * chunk : nparts;
-            for (int64_t b = grp * chunk; b < b1; ++b) {
-                const double2 v = parts[(b * Jpad + j) * n + k];
-                sr += v.x;
-                si += v.y;
+            // Eight loads in flight, then their sums in slot order.
+            for (int64_t b = grp * chunk; b < b1; b += 8) {
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[u] = (b + u < b1) ? parts[((b + u) * Jpad + j) * n + k] : make_double2(0.0, 0.0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    sr += v[u].x;
+                    si += v[u].y;
+                }
             }
         }
         part[grp][el] = make_double2(sr, si);
