@@ -34,12 +34,14 @@ def launch_names(workload: str, precision: str, budget: int = 0):
     plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
                   support_max=s.support_max)
     # Graph replays of single-block plans with several orders run the orders concurrently;
-    # their dispatch order is the capture order: every order's launches, then the partial
-    # sums of every order (the workloads here fit the per-order workspace of that mode).
+    # their dispatch order is the capture order: every order's launches, highest order first,
+    # then the partial sums of every order in ascending order (the workloads here fit the
+    # per-order workspace of that mode).
     concurrent = plan.n_blocks == 1 and s.order_max >= 3
     names = ["prepare"]
     reduces = []
-    for M in range(2, s.order_max + 1):
+    orders = range(s.order_max, 1, -1) if concurrent else range(2, s.order_max + 1)
+    for M in orders:
         sparse = s.support.get(M) is not None and M not in s.hashed
         tucker = sparse and 1 <= s.support_max <= 8 and (
             (M == 3 and (s.n > 64 or precision == "fp64")) or (M == 2 and s.n > 96))
@@ -58,7 +60,7 @@ def launch_names(workload: str, precision: str, budget: int = 0):
             names.append(f"o{M}_fused")
             (reduces if concurrent else names).append(f"o{M}_reduce")
     plan.close()
-    return names + reduces
+    return names + sorted(reduces)
 
 
 def _dispatches(path):

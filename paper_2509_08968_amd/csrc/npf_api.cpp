@@ -385,7 +385,10 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
                                              (M == plan->N && npf_out) ? &fin : nullptr),
                          "partial sums");
     };
-    for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
+    // Concurrent runs enqueue the highest order (the longest chain, on the caller's stream)
+    // first, so that its launches are not queued behind the shorter orders'.
+    for (int q = 0; q <= plan->N - 2 && rc == NPF_OK; ++q) {
+        const int M = concurrent ? plan->N - q : 2 + q;
         const bool on_side = concurrent && M < plan->N;
         const hipStream_t sm = on_side ? cs->side[M] : s;
         if (on_side && (rc = check_hip(hipStreamWaitEvent(sm, cs->ev_start, 0), "fork"))) break;
