@@ -99,8 +99,7 @@ int run_rows(const npf_plan_s *p, int M, const npf_tensor *A, const void *V, voi
 // T_{M-1} of the block [j0, j0 + J) in buffer (M-1) % 2: the upper-index contraction and
 // the chain stages, or Psi applied to the per-row tables (tucker: run_rows done).
 int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tensor *A,
-              const void *U, const void *V, void *ws, hipStream_t s, bool tucker = false,
-              hipEvent_t before_stages = nullptr)
+              const void *U, const void *V, void *ws, hipStream_t s, bool tucker = false)
 {
     if (tucker) {
         Timed t(p, kname(M, "tucker_psi"), s);
@@ -115,9 +114,6 @@ int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tenso
         Timed t(p, kname(M, "psi_a"), s);
         rc = check_hip(launch_psi_a(a), "upper-index contraction");
     }
-    // The upper-index contraction needs only the inputs; the stages also need the staged
-    // operands (concurrent runs stage them on another stream meanwhile).
-    if (!rc && before_stages) rc = check_hip(hipStreamWaitEvent(s, before_stages, 0), "join");
     const bool mfma = stage_mfma_supported(p);
     for (int i = 1; rc == NPF_OK && i < M; ++i) {
         Timed t(p, kname(M, "stage", i), s);
@@ -244,8 +240,8 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
 // first concurrent capture and kept for the life of the process, since the cached graphs
 // captured from them outlive the plans.  Used only while capturing, under g_graph_mu.
 struct SideSet {
-    hipStream_t side[NPF_MAX_ORDER + 1] = {};   // side[1]: operand staging; side[M]: order M
-    hipEvent_t ev_start = nullptr, ev_prep = nullptr, ev_done[NPF_MAX_ORDER + 1] = {};
+    hipStream_t side[NPF_MAX_ORDER + 1] = {};   // side[M]: order M
+    hipEvent_t ev_start = nullptr, ev_done[NPF_MAX_ORDER + 1] = {};
     bool ok = false;
 };
 
@@ -280,15 +276,13 @@ const SideSet *side_set()
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     SideSet &S = g_side[dev];
     if (S.ok) return &S;
-    for (int M = 1; M < NPF_MAX_ORDER; ++M)
+    for (int M = 2; M < NPF_MAX_ORDER; ++M)
         if (!S.side[M] && hipStreamCreateWithFlags(&S.side[M], hipStreamNonBlocking) != hipSuccess)
             return nullptr;
     for (int M = 2; M <= NPF_MAX_ORDER; ++M)
         if (!S.ev_done[M] && hipEventCreateWithFlags(&S.ev_done[M], hipEventDisableTiming) != hipSuccess)
             return nullptr;
     if (!S.ev_start && hipEventCreateWithFlags(&S.ev_start, hipEventDisableTiming) != hipSuccess)
-        return nullptr;
-    if (!S.ev_prep && hipEventCreateWithFlags(&S.ev_prep, hipEventDisableTiming) != hipSuccess)
         return nullptr;
     S.ok = true;
     return &S;
@@ -357,21 +351,18 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
               const SideSet *cs)
 {
     const bool concurrent = cs != nullptr;
-    // Concurrent (captured runs of single-block plans with several orders): the operands are
-    // staged on side stream 1 while every order starts its upper-index contraction; order
-    // M < N runs its chain and last stage on side stream M; the partial sums of every order
-    // run on the main stream, in order, after that order's last stage.
+    // Concurrent (captured runs of single-block plans with several orders): after the operand
+    // staging, order M < N runs its chain and last stage on side stream M while order N runs
+    // on the caller's stream; the partial sums of every order run on the caller's stream, in
+    // order, after that order's last stage.
     int rc = NPF_OK;
     char *w = static_cast<char *>(ws);
     const int64_t nn = plan->n * plan->n;
-    if (concurrent) {
-        rc = check_hip(hipEventRecord(cs->ev_start, s), "fork");
-        if (!rc) rc = check_hip(hipStreamWaitEvent(cs->side[1], cs->ev_start, 0), "fork");
-        if (!rc) rc = stage_operands(plan, U, V, ws, cs->side[1]);
-        if (!rc) rc = check_hip(hipEventRecord(cs->ev_prep, cs->side[1]), "fork");
-    } else {
-        rc = stage_operands(plan, U, V, ws, s);
-    }
+    // Operand staging first on the caller's stream; concurrent runs fork after it (a
+    // dependency of the chains on staging work queued on another stream was seen to hold the
+    // longest chain behind the other orders' kernels).
+    rc = stage_operands(plan, U, V, ws, s);
+    if (!rc && concurrent) rc = check_hip(hipEventRecord(cs->ev_start, s), "fork");
     auto reduce = [&](int M, int64_t j0, int64_t J, hipStream_t st) {
         const OrderLayout ol(plan, M);
         double *PM = P_out ? static_cast<double *>(P_out) + 2 * (M - 2) * nn
@@ -394,13 +385,11 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
         if (on_side && (rc = check_hip(hipStreamWaitEvent(sm, cs->ev_start, 0), "fork"))) break;
         const OrderLayout ol(plan, M);
         const bool tucker = tucker_supported(plan, &A[M - 2], M);
-        if (tucker && concurrent) rc = check_hip(hipStreamWaitEvent(sm, cs->ev_prep, 0), "join");
-        if (!rc && tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, sm);
+        if (tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, sm);
         for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
             int64_t j0, J;
             block_modes(plan, b, j0, J);
-            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, sm, tucker,
-                           (concurrent && !tucker) ? cs->ev_prep : nullptr);
+            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, sm, tucker);
             if (rc) break;
             {
                 Timed t(plan, kname(M, "fused"), sm);
