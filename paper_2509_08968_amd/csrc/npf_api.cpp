@@ -352,9 +352,8 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
 {
     const bool concurrent = cs != nullptr;
     // Concurrent (captured runs of single-block plans with several orders): after the operand
-    // staging, order M < N runs its chain and last stage on side stream M while order N runs
-    // on the caller's stream; the partial sums of every order run on the caller's stream, in
-    // order, after that order's last stage.
+    // staging, order M < N runs its chain, last stage and partial sums on side stream M while
+    // order N runs on the caller's stream; the partial sums follow the order of M.
     int rc = NPF_OK;
     char *w = static_cast<char *>(ws);
     const int64_t nn = plan->n * plan->n;
@@ -399,12 +398,17 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
             }
             if (!rc && !concurrent) rc = reduce(M, j0, J, s);
         }
-        if (!rc && concurrent) rc = check_hip(hipEventRecord(cs->ev_done[M], sm), "join");
     }
+    // Partial sums of a concurrent run: order M < N on its side stream right after its last
+    // stage and after order M - 1's sums (the NPF sum is accumulated in order), the highest
+    // order's on the caller's stream after order N - 1's -- so only the last one follows the
+    // longest chain.
     if (concurrent)
         for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
-            rc = check_hip(hipStreamWaitEvent(s, cs->ev_done[M], 0), "join");
-            if (!rc) rc = reduce(M, 0, plan->n, s);
+            const hipStream_t sm = M < plan->N ? cs->side[M] : s;
+            if (M > 2) rc = check_hip(hipStreamWaitEvent(sm, cs->ev_done[M - 1], 0), "join");
+            if (!rc) rc = reduce(M, 0, plan->n, sm);
+            if (!rc && M < plan->N) rc = check_hip(hipEventRecord(cs->ev_done[M], sm), "join");
         }
     return rc;
 }
