@@ -5,8 +5,6 @@ namespace npf {
 
 namespace {
 
-constexpr int kThreads = kBf3Threads;
-
 // ------------------------------------------------------------------ one chain stage, n > 64
 // Same arithmetic as stage_bf3; a workgroup owns a range of TT t-tiles (grid.z) and keeps
 // only that slice of the Phi^T planes in LDS.  NW waves: WPI = NW / IPW waves per item (one
