@@ -401,8 +401,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the hot path is not sharded across GPUs in this "
-              "build (the design for sharding by output mode is described in DESIGN.md).",
+        print("bench.py measures one GPU only: the hot path is not sharded across GPUs "
+              "(it would shard by output-mode block; each GPU's share runs as here).",
               file=sys.stderr)
         sys.exit(2)
 

@@ -47,7 +47,7 @@ extern "C" {
 #define NPF_E_INVALID 1     /* bad argument, shape or size                        */
 #define NPF_E_BUDGET 2      /* the memory budget is below the smallest block      */
 #define NPF_E_DEVICE 3      /* a HIP call or kernel launch failed                 */
-#define NPF_E_UNSUPPORTED 4 /* valid request this build cannot serve              */
+#define NPF_E_UNSUPPORTED 4 /* valid request the library does not serve           */
 
 #define NPF_MAX_ORDER 6     /* largest N                                           */
 #define NPF_ALL_BLOCKS (-1)
