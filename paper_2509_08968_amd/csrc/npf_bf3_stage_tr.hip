@@ -57,6 +57,15 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
     const uint32_t jp = uint32_t(a.Jpad);
     const int nn = int(a.n);
     const int64_t istride = int64_t(bp.gx) * IPW;
+    // Items are prefix-major and prefixes in colex order, i.e. by their last element first:
+    // the items with some t >= last(p) in this slice are the first nitems, those whose prefix
+    // has its last element below t_base + TW (binom(L + i - 2, i - 1) prefixes, L that bound).
+    const int64_t nitems = [&] {
+        if (a.i < 2) return a.items;
+        const int64_t L = (t_base + TW < nn) ? t_base + TW : nn;
+        const int64_t np = colex_term_c(L, a.i - 1);
+        return np * a.U_suf < a.items ? np * a.U_suf : a.items;
+    }();
 
     // Tables of the items ib .. ib + IPW - 1 into buffer buf.
     auto build = [&](int64_t ib, int buf) {
@@ -64,7 +73,7 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
             const int q = xq / NP;
             const int x = xq - q * NP;
             const int64_t itq = ib + q;
-            if (itq >= a.items) {
+            if (itq >= nitems) {
                 if (x == 0) sm[buf][q] = -1;
                 continue;
             }
@@ -103,17 +112,17 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
     int64_t ib = int64_t(bp.x) * IPW;
     int buf = 0;
     float2 ring[PD][8];       // slot kc % PD: chunk kc of the current item, then kc + PD
-    if (ib < a.items) build(ib, 0);
+    if (ib < nitems) build(ib, 0);
     else if (threadIdx.x < IPW) sm[0][threadIdx.x] = -1;
     __syncthreads();          // also orders the LDS slice of Phi
     if (wave_on && active(sm[0][islot])) {
 #pragma unroll
         for (int kc = 0; kc < PD; ++kc) load_chunk(X + sbase[0][islot][0], sidx[0][islot], kc, ring[kc]);
     }
-    for (; ib < a.items; ib += istride, buf = (buf == 2) ? 0 : buf + 1) {
+    for (; ib < nitems; ib += istride, buf = (buf == 2) ? 0 : buf + 1) {
         const int64_t ibn = ib + istride;
         const int nbuf = (buf == 2) ? 0 : buf + 1;
-        if (ibn < a.items) build(ibn, nbuf);
+        if (ibn < nitems) build(ibn, nbuf);
         else if (threadIdx.x < IPW) sm[nbuf][threadIdx.x] = -1;
         __syncthreads();
         const int m = sm[buf][islot];
