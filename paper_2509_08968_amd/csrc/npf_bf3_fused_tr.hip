@@ -95,19 +95,26 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
     // The item loop is uniform over the workgroup (it holds two barriers).
     const int64_t ib0 = int64_t(bp.x) * IPW;
     int64_t it = ib0 + islot;
-    uint64_t pk = (it < a.items) ? a.ptab[it] : 0;
+    // Prefixes are in colex order (by their last element first): those with some t >=
+    // last(p) in this slice are the first binom(L + M - 3, M - 2), L = min(t_base + 32, n).
+    const int64_t nitems = [&] {
+        const int64_t L = (t_base + 32 < nn) ? t_base + 32 : nn;
+        const int64_t np = colex_term_c(L, M - 1);
+        return np < a.items ? np : a.items;
+    }();
+    uint64_t pk = (it < nitems) ? a.ptab[it] : 0;
     float2 cur[8];
-    if (wave_on && it < a.items && active(pk)) load_chunk(it, kc0, cur);
-    for (int64_t ib = ib0; ib < a.items; ib += istride, it += istride) {
+    if (wave_on && it < nitems && active(pk)) load_chunk(it, kc0, cur);
+    for (int64_t ib = ib0; ib < nitems; ib += istride, it += istride) {
         // An offset the compiler cannot see through: the slices' fragments are read from LDS
         // in every iteration rather than hoisted into registers for the whole loop.
         int lo = 0;
         asm volatile("" : "+s"(lo));
         const __bf16 *Lp = Lphi + lo, *Lq = Lz + lo;
         const int64_t itn = it + istride;
-        const uint64_t pkn = (itn < a.items) ? a.ptab[itn] : 0;
-        const bool next_on = wave_on && itn < a.items && active(pkn);
-        const bool on = wave_on && it < a.items && active(pk);
+        const uint64_t pkn = (itn < nitems) ? a.ptab[itn] : 0;
+        const bool next_on = wave_on && itn < nitems && active(pkn);
+        const bool on = wave_on && it < nitems && active(pk);
         v4f sr[2], si[2], srl[2], sil[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) sr[u] = si[u] = srl[u] = sil[u] = v4f{0, 0, 0, 0};
