@@ -23,3 +23,9 @@ PARITY_CASES = {
     "n72-o3-dense": lambda: I.dense_system(72, [2, 3], 3107),
     "n130-o2-dense": lambda: I.dense_system(130, [2], 3108),
 }
+
+# Plans beyond four orders (the largest order the API accepts is six).
+HIGH_ORDER_CASES = {
+    "n18-o5-dense": lambda: I.dense_system(18, [2, 3, 4, 5], 3109),
+    "n11-o6-dense": lambda: I.dense_system(11, [2, 3, 4, 5, 6], 3110),
+}

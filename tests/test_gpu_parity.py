@@ -9,7 +9,7 @@ import pytest
 import oracle
 from paper_2509_08968_amd import binding as B
 from paper_2509_08968_amd import inputs as I
-from tests.helpers import PARITY_CASES, rel
+from tests.helpers import HIGH_ORDER_CASES, PARITY_CASES, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -207,3 +207,50 @@ def test_workload_n128_o4_dense_sampled(torch_dev, dense128, precision):
     z = np.stack([s.delta * s.U[i, :] for i in modes])          # [modes, states]
     npf_cols = s.V[:, modes] * (z + sum(ref.values())).T
     assert rel(npf[:, modes], npf_cols) <= TOL[precision]
+
+
+# Mixed paths beyond four orders.  C is rounded to FP32 once per sorted tuple, and the
+# symmetric packing then reuses that one rounding for each of the tuple's m(t) <= M!
+# orderings, so its error enters P coherently instead of averaging over M! independent
+# roundings.  A CPU emulation of exactly that arithmetic (complex64 chain, C read at the sorted
+# representative, divide and reduction in FP64) gives relative P errors of 5.6e-7 (M = 3),
+# 5.5e-7 (M = 4) and 1.0e-6 (M = 5) on the n = 18 system below, against 1.5e-7 to 2.1e-7 when
+# every ordering is rounded on its own; the bound is 2.5 times the largest emulated value.
+# FP64 keeps its 1e-10 at every order.
+TOL_HIGH_ORDER_MIXED = 2.6e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", sorted(HIGH_ORDER_CASES))
+def test_high_orders_match_oracle(torch_dev, case, precision):
+    torch, dev = torch_dev
+    s = HIGH_ORDER_CASES[case]()
+    print(f"[high orders] {case} {precision}", flush=True)
+    ref, npf_ref = _oracle_all(s)
+    npf, Ps = B.compute(s, precision, dev)
+    tol = TOL["fp64"] if precision == "fp64" else TOL_HIGH_ORDER_MIXED
+    for M in s.orders:
+        assert rel(Ps[M], ref[M]["P"]) <= tol, f"P_{M}"
+    assert rel(npf, npf_ref) <= tol, "npf"
+
+
+@pytest.mark.parametrize("case", sorted(HIGH_ORDER_CASES))
+def test_high_orders_staged_steps_fp64(torch_dev, case):
+    torch, dev = torch_dev
+    s = HIGH_ORDER_CASES[case]()
+    print(f"[high orders staged fp64] {case}", flush=True)
+    ref, _ = _oracle_all(s)
+    d = B.upload_system(s, dev)
+    plan = B.Plan(s.n, s.order_max, "fp64", s.eps, s.tau, s.delta)
+    ws = plan.workspace(dev)
+    for M in s.orders:
+        C = torch.empty((s.n, plan.unique_tuples[M]), dtype=torch.complex128, device=dev)
+        plan.modal_contract(M, B.NPF_ALL_BLOCKS, d.tensors[M - 2], d.U, d.V, ws, C)
+        torch.cuda.synchronize()
+        assert rel(C.cpu().numpy(), ref[M]["C"]) <= TOL["fp64"], f"C_{M}"
+        plan.normal_form(M, B.NPF_ALL_BLOCKS, d.lam, C)
+        P = torch.zeros((s.n, s.n), dtype=torch.complex128, device=dev)
+        plan.assemble(M, B.NPF_ALL_BLOCKS, C, d.U, P)
+        torch.cuda.synchronize()
+        assert rel(P.cpu().numpy(), ref[M]["P"]) <= TOL["fp64"], f"P_{M}"
+    plan.close()
