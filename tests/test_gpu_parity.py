@@ -254,3 +254,33 @@ def test_high_orders_staged_steps_fp64(torch_dev, case):
         torch.cuda.synchronize()
         assert rel(P.cpu().numpy(), ref[M]["P"]) <= TOL["fp64"], f"P_{M}"
     plan.close()
+
+
+def _zero_order3():
+    s = I.block_sparse_system(24, [2, 3], 3111)
+    s.A[3] = np.zeros_like(s.A[3])          # sent sparse: no columns at all
+    return s
+
+
+EMPTY_CASES = {
+    "n24-o3-zero-tensor": _zero_order3,
+    "n10-o2o4-missing-o3": lambda: I.dense_system(10, [2, 4], 3112),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", sorted(EMPTY_CASES))
+def test_empty_tensor_gives_zero_order(torch_dev, case, precision):
+    """A derivative tensor with no entries (an all-zero tensor sent sparse, or an order the
+    system does not have) contributes exactly nothing: P_3 is zero bit for bit, the other
+    orders and the NPF match the oracle.  The upper index goes first on every order."""
+    s = EMPTY_CASES[case]()
+    print(f"[empty tensor] {case} {precision}", flush=True)
+    ref = {M: oracle.sym(s, M) for M in s.orders}
+    npf_ref = oracle.assemble(s, sum(r["P"] for r in ref.values()))
+    npf, Ps = B.compute(s, precision, support_max=0)
+    assert not np.any(Ps[3]), "P_3 must be exactly zero"
+    for M in s.orders:
+        if M != 3:
+            assert rel(Ps[M], ref[M]["P"]) <= TOL[precision], f"P_{M}"
+    assert rel(npf, npf_ref) <= TOL[precision], "NPF"

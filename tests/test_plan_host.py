@@ -69,6 +69,7 @@ def test_plan_counts_and_entries():
     (dict(n=8, order_max=2, tau=-1.0), B.NPF_E_INVALID),
     (dict(n=8, order_max=2, budget_bytes=-5), B.NPF_E_INVALID),
     (dict(n=128, order_max=4, budget_bytes=1 << 20), B.NPF_E_BUDGET),
+    (dict(n=257, order_max=2), B.NPF_E_UNSUPPORTED),
 ])
 def test_plan_rejects(kw, code):
     with pytest.raises(B.NpfError) as e:
@@ -88,3 +89,10 @@ def test_plan_budget_shrinks_mode_blocks():
 def test_plan_explicit_block_size():
     p = B.Plan(40, 2, "fp64", block_modes=16)
     assert p.n_blocks == 3 and p.block_modes == 14
+
+
+def test_plan_accepts_the_largest_size():
+    p = B.Plan(256, 4, "bf16x3")
+    assert p.unique_tuples[4] == 259 * 258 * 257 * 256 // 24
+    assert p.block_modes * p.n_blocks >= 256
+    p.close()
