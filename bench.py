@@ -244,6 +244,18 @@ BATCH_WORKLOAD = "batch256-o3-blocksparse"
 BATCH_BUDGET = 128 << 30
 
 
+def copy_probe(args, device):
+    """One device copy of --copy-probe-mib MiB before the workload: the reference that the
+    HBM counter summaries scale every dispatch by."""
+    import torch
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+
 def bench_batch(args):
     """256 block-sparse systems (n uniform over even values in [32, 160], orders 2-3) in one
     batched call per step, replayed as a graph; per-system solo rates beside it."""
@@ -257,6 +269,7 @@ def bench_batch(args):
     device = "cuda:0"
     torch.cuda.set_device(0)
     B.lib()
+    copy_probe(args, device)
     t0 = time.perf_counter()
     ss = I.workload_batch()
     devs = [B.upload_system(s, device) for s in ss]
@@ -419,12 +432,7 @@ def main():
     device = "cuda:0"
     torch.cuda.set_device(0)
     B.lib()
-    if args.copy_probe_mib:
-        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=device)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    copy_probe(args, device)
     s = I.WORKLOADS[args.workload]()
     sysm = B.upload_system(s, device)
     log(f"[bench] workload {args.workload}: n={s.n} orders={s.orders}")

@@ -63,6 +63,29 @@ def launch_names(workload: str, precision: str, budget: int = 0):
     return names + sorted(reduces)
 
 
+def batch_launch_names(workload: str):
+    """Names of the shared (multi-system) launches of one batched step, in dispatch order,
+    as bench.py names them: w<wave>_np<padded n>_o<order>_stage<i> | _fused.  Every chain
+    stage and last stage of a batch runs in one of these launches (the kernels whose names end
+    in _multi); the per-system launches around them are not named here.  The launch records
+    are listed by wave, padded size, order and stage; a run launches them by wave, order and
+    stage (the fused last stage after stage M-1), each over the padded sizes in turn."""
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    from . import binding as B
+    from . import inputs as I
+    if workload != bench.BATCH_WORKLOAD:
+        raise ValueError(f"not a batched workload: {workload}")
+    b = B.Batch(I.workload_batch(), bench.BATCH_BUDGET)
+    recs = b.launches()
+    b.close()
+    order = sorted(range(len(recs)), key=lambda q: (
+        recs[q]["wave"], recs[q]["order"],
+        recs[q]["stage"] if recs[q]["kind"] == 0 else recs[q]["order"], q))
+    return [f"w{recs[q]['wave']}_np{recs[q]['npad']}_o{recs[q]['order']}_" +
+            (f"stage{recs[q]['stage']}" if recs[q]["kind"] == 0 else "fused") for q in order]
+
+
 def _dispatches(path):
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: int(r["Dispatch_Id"]))
@@ -76,17 +99,24 @@ def _scale(disp, copy_mib):
 
 
 def traffic(workload, precision, fetch_csv, write_csv, copy_mib, budget=0):
-    names = launch_names(workload, precision, budget)
+    batched = workload.startswith("batch")
+    names = batch_launch_names(workload) if batched else launch_names(workload, precision, budget)
     out = {}
     for ctr, path in (("fetch", fetch_csv), ("write", write_csv)):
         disp = _dispatches(path)
         f = _scale(disp, copy_mib)
-        lib = [(k, v) for k, v in disp if "npf::" in k]
+        lib = [(k, v) for k, v in disp if "npf::" in k and (not batched or "_multi" in k)]
         steps = len(lib) // len(names)
         acc = defaultdict(list)
         for s in range(steps):
             for i, nm in enumerate(names):
                 k, v = lib[s * len(names) + i]
+                if batched:
+                    # the symbol must be the named kind of kernel at the named padded size
+                    kind = "fused" if nm.endswith("fused") else "stage"
+                    npad = nm.split("_")[1][2:]
+                    if kind not in k or f"<{npad}," not in k:
+                        raise ValueError(f"dispatch {k[:80]} does not match launch {nm}")
                 acc[nm].append((k, v * f * 1024.0))
         for nm, vals in acc.items():
             d = out.setdefault(nm, {"symbol": vals[0][0][:100]})
