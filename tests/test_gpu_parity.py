@@ -152,6 +152,36 @@ def test_graph_replay_matches_eager(torch_dev):
     assert torch.allclose(Pg, 2.0 * ref_P, rtol=1e-5, atol=0)
 
 
+# Kept before test_many_plans_share_graph_cache: that test fills the library's graph cache,
+# after which new argument sets run eagerly.
+@pytest.mark.parametrize("precision", ["bf16x3", "fp64"])
+@pytest.mark.parametrize("case", sorted(HIGH_ORDER_CASES))
+def test_high_orders_graph_replay_matches_eager(torch_dev, case, precision):
+    """Five and six orders run concurrently inside the replayed graph (a side stream for
+    every order below N, the partial sums chained in order): every replay equals the eager
+    run bitwise."""
+    torch, dev = torch_dev
+    s = HIGH_ORDER_CASES[case]()
+    print(f"[graph replay high orders] {case} {precision}", flush=True)
+    d = B.upload_system(s, dev)
+    n, N = s.n, s.order_max
+    pe = B.Plan(n, N, precision, s.eps, s.tau, s.delta, graph=False)
+    pg = B.Plan(n, N, precision, s.eps, s.tau, s.delta, graph=True)
+    ws_e, ws_g = pe.workspace(dev), pg.workspace(dev)
+    st = torch.cuda.Stream()
+    Pe = torch.empty((N - 1, n, n), dtype=torch.complex128, device=dev)
+    Ne = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    Pg, Ng = torch.empty_like(Pe), torch.empty_like(Ne)
+    pe.run(d.tensors, d.U, d.V, d.lam, ws_e, Pe, Ne, st)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        pg.run(d.tensors, d.U, d.V, d.lam, ws_g, Pg, Ng, st)
+        torch.cuda.synchronize()
+        assert torch.equal(Pg, Pe) and torch.equal(Ng, Ne), rep
+    pg.close()
+    pe.close()
+
+
 def test_many_plans_share_graph_cache(torch_dev):
     """More concurrent-order plans than npf_run keeps graphs for, one after another: each
     runs (captured and replayed while the cache has room, eagerly after that), is checked
