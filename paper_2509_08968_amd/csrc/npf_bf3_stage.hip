@@ -70,8 +70,16 @@ __device__ __forceinline__ void stage_bf3_body(const Bf3Args &a, const BlockPos 
     if (it < a.items && wave_on) gather_x(it, 0);
     for (; it < a.items; it += bp.gx, buf ^= 1) {
         Split3 xr[KC], xi[KC], xn_[KC];
+        // Chunks of 32 gathered rows that are zero across the wave add nothing to the
+        // products and are skipped (block-sparse tensors leave most of them zero in the
+        // first stages: a row is nonzero only if its states share a support block).
+        int live = 0;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
+            bool nz = false;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) nz = nz || xn[kc][s].x != 0.f || xn[kc][s].y != 0.f;
+            if (__any(nz)) live |= 1 << kc;
             split_x(xn[kc], xr[kc], xi[kc]);
             xn_[kc] = negx3(xi[kc]);
         }
@@ -94,6 +102,7 @@ __device__ __forceinline__ void stage_bf3_body(const Bf3Args &a, const BlockPos 
             if (tt < tt0) continue;
 #pragma unroll
             for (int kc = 0; kc < KC; ++kc) {
+                if (!((live >> kc) & 1)) continue;
                 Split3 pr, pi;
                 phi_frags<NP>(Lphi, kc * 32, tt * 16 + c, g, pr, pi);
                 mm6s(pr, xr[kc], sr[tt], srl[tt]);
