@@ -20,6 +20,7 @@ usage: python -m paper_2509_08968_amd.counters trace WORKLOAD PRECISION STATS_CS
 from __future__ import annotations
 
 import csv
+import functools
 import json
 import os
 import sys
@@ -63,6 +64,7 @@ def launch_names(workload: str, precision: str, budget: int = 0):
     return names + sorted(reduces)
 
 
+@functools.lru_cache(maxsize=None)
 def batch_launch_names(workload: str):
     """Names of the shared (multi-system) launches of one batched step, in dispatch order,
     as bench.py names them: w<wave>_np<padded n>_o<order>_stage<i> | _fused.  Every chain
@@ -82,8 +84,8 @@ def batch_launch_names(workload: str):
     order = sorted(range(len(recs)), key=lambda q: (
         recs[q]["wave"], recs[q]["order"],
         recs[q]["stage"] if recs[q]["kind"] == 0 else recs[q]["order"], q))
-    return [f"w{recs[q]['wave']}_np{recs[q]['npad']}_o{recs[q]['order']}_" +
-            (f"stage{recs[q]['stage']}" if recs[q]["kind"] == 0 else "fused") for q in order]
+    return tuple(f"w{recs[q]['wave']}_np{recs[q]['npad']}_o{recs[q]['order']}_" +
+                 (f"stage{recs[q]['stage']}" if recs[q]["kind"] == 0 else "fused") for q in order)
 
 
 def _dispatches(path):
