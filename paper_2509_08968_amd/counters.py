@@ -14,6 +14,7 @@ scatter) and stages 1..M-1, or the per-row Psi step; the fused last stage; one p
 launch (which also writes the NPF for the last order).
 
 usage: python -m paper_2509_08968_amd.counters trace WORKLOAD PRECISION STATS_CSV OUT_DIR CMD
+       python -m paper_2509_08968_amd.counters sq WORKLOAD PRECISION COUNTER_CSV OUT_DIR CMD
        python -m paper_2509_08968_amd.counters traffic WORKLOAD PRECISION FETCH_CSV WRITE_CSV
            COPY_MIB OUT_DIR CMD...
 """
@@ -171,6 +172,48 @@ def write_traffic(workload, precision, fetch_csv, write_csv, copy_mib, out_dir, 
         f.write("\n".join(lines) + "\n")
 
 
+SQ_COUNTERS = ("SQ_WAVE_CYCLES", "SQ_BUSY_CU_CYCLES", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_INSTS_VALU",
+               "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_WAIT_INST_ANY", "SQ_LDS_BANK_CONFLICT")
+
+
+def write_sq(workload, precision, csv_path, out_dir, cmd, budget=0):
+    """Instruction-mix summary of one rocprofv3 --pmc pass over SQ_COUNTERS
+    (profiles/sq_mix_<workload>_<precision>.txt): per launch of each kernel of a step, the
+    ratios that do not depend on how the counters are normalised over SIMDs and XCDs."""
+    names = launch_names(workload, precision, budget)
+    per = defaultdict(dict)                      # dispatch id -> {counter: value}
+    kern = {}
+    for r in csv.DictReader(open(csv_path)):
+        d = int(r["Dispatch_Id"])
+        per[d][r["Counter_Name"]] = per[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        kern[d] = r["Kernel_Name"]
+    lib = [d for d in sorted(per) if "npf::" in kern[d]]
+    steps = len(lib) // len(names)
+    acc = defaultdict(lambda: defaultdict(float))
+    for s in range(steps):
+        for i, nm in enumerate(names):
+            for c, v in per[lib[s * len(names) + i]].items():
+                acc[nm][c] += v
+    lines = [f"# SQ instruction mix per kernel, {workload}, {precision}",
+             "# command (repo root, TMPDIR=/tmp):", f"#   {cmd}",
+             "# valu/mfma, lds/mfma: instructions issued per MFMA instruction; mfma_busy/cu_busy:",
+             "#   SQ_VALU_MFMA_BUSY_CYCLES / SQ_BUSY_CU_CYCLES (both summed by the counter block);",
+             "#   wait/wave: SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; conflicts/lds: bank-conflict cycles",
+             "#   per LDS instruction",
+             "# kernel  valu/mfma  lds/mfma  mfma_busy/cu_busy  wait/wave  conflicts/lds  mfma_insts"]
+    for nm in dict.fromkeys(names):
+        a = acc[nm]
+        mf = a.get("SQ_INSTS_MFMA", 0.0)
+        q = lambda x, y: (a.get(x, 0.0) / a[y]) if a.get(y) else float("nan")
+        lines.append(f"{nm:22s} {q('SQ_INSTS_VALU', 'SQ_INSTS_MFMA'):9.2f} "
+                     f"{q('SQ_INSTS_LDS', 'SQ_INSTS_MFMA'):9.2f} "
+                     f"{q('SQ_VALU_MFMA_BUSY_CYCLES', 'SQ_BUSY_CU_CYCLES'):9.3f} "
+                     f"{q('SQ_WAIT_INST_ANY', 'SQ_WAVE_CYCLES'):9.3f} "
+                     f"{q('SQ_LDS_BANK_CONFLICT', 'SQ_INSTS_LDS'):9.3f} {mf / max(steps, 1):12.4g}")
+    with open(os.path.join(out_dir, f"sq_mix_{workload}_{precision}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv):
     mode = argv[0]
     if mode == "trace":
@@ -179,8 +222,13 @@ def main(argv):
     elif mode == "traffic":
         workload, precision, fetch_csv, write_csv, copy_mib, out_dir = argv[1:7]
         write_traffic(workload, precision, fetch_csv, write_csv, copy_mib, out_dir, argv[7:])
+    elif mode == "sq":
+        workload, precision, csv_path, out_dir, cmd = argv[1:6]
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import bench
+        write_sq(workload, precision, csv_path, out_dir, cmd, bench.budget_for(workload, precision))
     else:
-        raise SystemExit("usage: counters.py trace|traffic ...")
+        raise SystemExit("usage: counters.py trace|traffic|sq ...")
 
 
 if __name__ == "__main__":
