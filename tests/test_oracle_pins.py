@@ -186,7 +186,7 @@ def _poly_field(A1, AM_full, M, x):
     return A1 @ x + T / math.factorial(M)
 
 
-@pytest.mark.parametrize("n,M", [(3, 2), (4, 2), (3, 3), (4, 3), (3, 4)])
+@pytest.mark.parametrize("n,M", [(3, 2), (4, 2), (3, 3), (4, 3), (3, 4), (5, 4), (4, 5), (3, 6)])
 def test_p7_polarization_finite_differences(n, M):
     s = small(n, M, 71 + 10 * n + M)
     AM_full = oracle.unpack_full(s.A[M], n, M)
@@ -207,6 +207,55 @@ def test_p7_polarization_finite_differences(n, M):
                 acc += (-1) ** (M - size) * g(y)
         C_fd[:, r] = acc / math.factorial(M)
     assert rel(C, C_fd) < 1e-11
+
+
+def _multiplicities(tups):
+    """Orderings of each sorted tuple: M! / prod(count_v!)."""
+    M = tups.shape[1]
+    out = np.empty(len(tups))
+    for r, t in enumerate(tups):
+        _, cnt = np.unique(t, return_counts=True)
+        out[r] = math.factorial(M) / np.prod([math.factorial(int(c)) for c in cnt])
+    return out
+
+
+@pytest.mark.parametrize("case,M", [("n18-o5", 5), ("n11-o6", 6), ("n72-o3", 3), ("n130-o2", 2),
+                                    ("n20-o3-resonant", 3)])
+def test_p7_sampled_tuples_at_parity_sizes(case, M):
+    """C of the packed oracle at the sizes and orders the GPU parity tests run, pinned on
+    sampled tuples by exact polarization of the homogeneous degree-M field
+    f_M(x) = (1/M!) A_M[x, .., x], evaluated from packed storage as
+    sum over sorted s of A_M[:, s] * orderings(s) * prod_i x[s_i]: no chain, no Psi-first
+    contraction, no sorted-prefix stages."""
+    from tests.helpers import HIGH_ORDER_CASES, PARITY_CASES
+    build = {"n18-o5": HIGH_ORDER_CASES["n18-o5-dense"], "n11-o6": HIGH_ORDER_CASES["n11-o6-dense"],
+             "n72-o3": PARITY_CASES["n72-o3-dense"], "n130-o2": PARITY_CASES["n130-o2-dense"],
+             "n20-o3-resonant": PARITY_CASES["n20-o3-resonant"]}[case]
+    s = build()
+    n = s.n
+    tups = I.sorted_tuples(n, M)
+    mult = _multiplicities(tups)
+    rng = np.random.default_rng(700 + M)
+    picks = sorted(set(rng.choice(len(tups), 6, replace=False).tolist()) | {0, len(tups) - 1})
+    modes = sorted({0, n // 2, n - 1})
+    C = oracle.sym(s, M, modes=modes, want_C=True)["C"]
+
+    def g(y):
+        x = s.V @ y
+        X = mult * np.prod(x[tups], axis=1)
+        return s.U[modes] @ (s.A[M] @ X) / math.factorial(M)
+
+    for r in picks:
+        t = tups[r]
+        acc = np.zeros(len(modes), complex)
+        for size in range(1, M + 1):
+            for S in itertools.combinations(range(M), size):
+                y = np.zeros(n, complex)
+                for i in S:
+                    y[t[i]] += 1.0
+                acc += (-1) ** (M - size) * g(y)
+        c_fd = acc / math.factorial(M)
+        assert rel(C[:, r], c_fd) < 1e-11, (case, r)
 
 
 # ------------------------------------------------------------------ P8
@@ -258,14 +307,40 @@ def test_p8_homological_residual_order(M):
 
 
 # ------------------------------------------------------------------ P10
-@pytest.mark.parametrize("n,M", [(2, 2), (5, 2), (8, 2), (3, 3), (6, 3), (8, 3), (4, 4), (6, 4)])
+def _abs_terms(h_full, zeta_abs, n, M):
+    """S[j, k] = sum over t in [n]^M of |h[j, t]| prod_i |zeta_k[t_i]|: the sum of the
+    magnitudes of the terms of P[j, k] (rounding-error scale of the reduction)."""
+    T = np.abs(h_full).reshape((n,) + (n,) * M)
+    S = np.empty((n, n))
+    for k in range(n):
+        X = T
+        for _ in range(M):
+            X = X @ zeta_abs[:, k]
+        S[:, k] = X
+    return S
+
+
+@pytest.mark.parametrize("n,M", [(2, 2), (5, 2), (8, 2), (16, 2), (72, 2), (3, 3), (6, 3), (8, 3),
+                                 (16, 3), (33, 3), (4, 4), (6, 4), (10, 4), (16, 4), (4, 5), (8, 5),
+                                 (3, 6), (6, 6)])
 def test_p10_full_equals_sym(n, M):
+    """The literal full-tensor tier (mode products in the paper's order, Psi last, the sum
+    over every t in [n]^M) against the packed tier.  C and h agree to a few units of
+    rounding; P element by element within the a-priori bound of two differently ordered
+    sums of n^M products of M + 1 factors, 2 gamma_(n^M + M) sum_t |term|, plus the
+    propagated difference of h."""
     s = small(n, M, 101 + 10 * n + M)
     f = oracle.full(s, M)
     y = oracle.sym(s, M, want_C=True, want_h=True)
     assert rel(y["C"], full_to_sorted(f["C"], n, M)) < 1e-13
     assert rel(y["h"], full_to_sorted(f["h"], n, M)) < 1e-13
-    assert rel(y["P"], f["P"]) < 1e-13
+    u = 2.0 ** -53
+    N = n ** M + M
+    gamma = N * u / (1 - N * u)
+    S = _abs_terms(f["h"], np.abs(s.delta * s.U), n, M)
+    bound = (2 * gamma + 1e-13) * S
+    assert np.all(np.abs(y["P"] - f["P"]) <= bound)
+    assert rel(y["P"], f["P"]) < 1e-12
 
 
 def test_p10_mode_subset_rows_match():
