@@ -13,9 +13,9 @@ first); per mode block: the upper-index contraction (two launches for sparse ten
 scatter) and stages 1..M-1, or the per-row Psi step; the fused last stage; one partial-sum
 launch (which also writes the NPF for the last order).
 
-usage: python -m paper_2509_08968_amd.counters trace WORKLOAD PRECISION STATS_CSV OUT_DIR CMD
-       python -m paper_2509_08968_amd.counters sq WORKLOAD PRECISION COUNTER_CSV OUT_DIR CMD
-       python -m paper_2509_08968_amd.counters traffic WORKLOAD PRECISION FETCH_CSV WRITE_CSV
+usage: python bench_counters.py trace WORKLOAD PRECISION STATS_CSV OUT_DIR CMD
+       python bench_counters.py sq WORKLOAD PRECISION COUNTER_CSV OUT_DIR CMD
+       python bench_counters.py traffic WORKLOAD PRECISION FETCH_CSV WRITE_CSV
            COPY_MIB OUT_DIR CMD...
 """
 from __future__ import annotations
@@ -30,8 +30,8 @@ from collections import defaultdict
 
 def launch_names(workload: str, precision: str, budget: int = 0):
     """Kernel names of one npf_run step, in dispatch order."""
-    from . import binding as B
-    from . import inputs as I
+    from paper_2509_08968_amd import binding as B
+    from paper_2509_08968_amd import inputs as I
     s = I.WORKLOADS[workload]()
     plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
                   support_max=s.support_max)
@@ -75,8 +75,8 @@ def batch_launch_names(workload: str):
     stage (the fused last stage after stage M-1), each over the padded sizes in turn."""
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
-    from . import binding as B
-    from . import inputs as I
+    from paper_2509_08968_amd import binding as B
+    from paper_2509_08968_amd import inputs as I
     if workload != bench.BATCH_WORKLOAD:
         raise ValueError(f"not a batched workload: {workload}")
     b = B.Batch(I.workload_batch(), bench.BATCH_BUDGET)
@@ -228,7 +228,7 @@ def main(argv):
         import bench
         write_sq(workload, precision, csv_path, out_dir, cmd, bench.budget_for(workload, precision))
     else:
-        raise SystemExit("usage: counters.py trace|traffic|sq ...")
+        raise SystemExit("usage: bench_counters.py trace|traffic|sq ...")
 
 
 if __name__ == "__main__":

@@ -57,6 +57,9 @@ extern "C" {
 #define NPF_FP32 1          /* FP32 operands, FP32 accumulation per tile           */
 #define NPF_BF16X3 2        /* FP32 values split in three BF16 terms, six products
                                per multiply, FP32 accumulation per tile            */
+/* NPF_FP32 and NPF_BF16X3 serve order_max <= 4 (npf_plan_create returns NPF_E_UNSUPPORTED
+ * above): C is held in FP32 once per sorted tuple and shared by all of the tuple's
+ * orderings, whose coherent error exceeds 1e-6 relative at orders 5 and 6. */
 
 /* Storage of one derivative tensor A_M (device memory). */
 #define NPF_SRC_DENSE 0     /* values[k*U_M + r]                                   */
@@ -97,7 +100,38 @@ typedef struct npf_problem {
                                   row's lower indices over its own states first and apply
                                   Psi after (a row with more states makes the results
                                   NaN).  0: no bound, the upper index first everywhere.   */
+    int32_t a_convention;      /* NPF_A_DERIVATIVE or NPF_A_TAYLOR (below)             */
+    int32_t reserved;          /* 0                                                    */
+    /* Output modes (the critical modes of Section III): the P_M rows and NPF columns of
+     * these modes only are computed and written; the rest of P_out and npf_out is left
+     * untouched.  n_modes = 0 (modes may be NULL) selects all n modes.  Otherwise
+     * modes[0 .. n_modes-1] are distinct indices in [0, n) (host memory, copied). */
+    int64_t n_modes;
+    const int64_t *modes;
+    /* Conjugate pairs of a real system (eq. (1) has real derivative tensors): conj_of[i]
+     * is the mode whose eigenvalue, right and left eigenvectors are the complex conjugates
+     * of mode i's (conj_of[i] = i for a real mode); host [n], an involution, or NULL.  For a
+     * real A_M, C, h, P_M and the NPF of mode conj_of[i] are then the conjugates of mode i's
+     * (with the tuple's modes conjugated too), so of each requested pair only the lower
+     * index is computed and the other's P row and NPF column are filled by conjugation
+     * (about half the work).  The caller vouches for the pairing; with host copies below
+     * the planner checks it. */
+    const int64_t *conj_of;
+    /* Optional host copies (complex128, the layouts of the compute calls) for the
+     * preconditions: |Psi Phi - I| <= check_tol entrywise (eigenvector normalisation of
+     * Alg. 2), and for conj_of: lam, Phi columns and Psi rows of paired modes conjugate to
+     * check_tol relative to their largest entry.  Any may be NULL (that check is skipped:
+     * host_U and host_V are needed for the first and for the eigenvector part of the
+     * second).  check_tol = 0 selects 1e-8. */
+    const void *host_U, *host_V, *host_lambda;
+    double check_tol;
 } npf_problem;
+
+/* Input convention of the derivative tensors (eq. (1) against Alg. 2 step 4). */
+#define NPF_A_DERIVATIVE 0  /* A_M holds the M-th derivatives; C carries the 1/M! of
+                               Alg. 2 step 4 (the Taylor coefficient is A_M / M!)   */
+#define NPF_A_TAYLOR 1      /* A_M holds the Taylor coefficients of eq. (1) as printed
+                               (x' = A1 x + A2 x x + ..): no 1/M! is applied        */
 
 /* npf_run replays a HIP graph of its launch sequence when called again with the same
  * problem, pointers, descriptors and stream (the graph is captured on the first call; up to
@@ -122,19 +156,29 @@ typedef struct npf_plan_report {
     int64_t n_blocks;                  /* ceil(n / J)  (the BC of Alg. 1 for mode j)   */
     int64_t unique_tuples[NPF_MAX_ORDER + 1];   /* U_M per order                       */
     int64_t modal_entries;             /* sum_M n * U_M, symmetric-unique entries      */
+    int64_t output_modes;              /* modes whose P rows / NPF columns are written */
+    int64_t computed_modes;            /* of which computed (the others by conjugation) */
 } npf_plan_report;
 
 /* Plan (host only, synchronous): validates the problem, fixes the output-mode block size
  * J under hbm_budget_bytes following the batch-size rule of Alg. 1 (steps 6-15) and the
- * workspace size.  Returns NPF_E_BUDGET if even the smallest block does not fit. */
+ * workspace size.  Blocks run over the computed modes (all n, or the output modes less
+ * the conjugates filled from their partners), in ascending order.  Returns NPF_E_BUDGET if
+ * even the smallest block does not fit, NPF_E_INVALID for a bad mode list, pairing or a
+ * failed precondition check (the message says which). */
 int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out);
 int npf_plan_info(npf_plan_t plan, npf_plan_report *report);
+/* The computed modes in block order (computed[c], c < computed_modes: block b holds
+ * c in [b*J, b*J + J)) and, per computed mode, the output mode filled by its conjugate
+ * (filled[c], -1 for none).  Either pointer may be NULL. */
+int npf_plan_modes(npf_plan_t plan, int64_t *computed, int64_t *filled);
 /* Releases the plan (host metadata only: runs already enqueued are unaffected, and the
  * graphs npf_run instantiated stay cached for later plans of the same problem). */
 void npf_plan_destroy(npf_plan_t plan);
 
-/* Alg. 2 steps 1-4 for output-mode block `block` (modes [block*J, min(n, block*J+J)))
- * of order M: writes C_out[jj*U_M + r] (complex128, jj = j - block*J) for the block's
+/* Alg. 2 steps 1-4 for output-mode block `block` (computed modes c in [block*J,
+ * min(computed_modes, block*J+J)), see npf_plan_modes; NPF_ALL_BLOCKS: all of them) of
+ * order M: writes C_out[jj*U_M + r] (complex128, jj = c - first block's c) for the block's
  * modes and every sorted tuple r.  U, V: Psi, Phi as above.  ws: device workspace of at
  * least workspace_bytes.  The contraction runs in the plan's precision. */
 int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block, const npf_tensor *A,
@@ -148,7 +192,9 @@ int npf_normal_form(npf_plan_t plan, int32_t order, int64_t block, const void *l
                     void *C_inout, void *stream);
 
 /* Alg. 2 steps 12-19 for the block: P_acc[j*n + k] += -sum_{sorted t} m(t) h[j,t]
- * prod_i delta Psi[t_i,k], with m(t) the number of orderings of t; FP64. */
+ * prod_i delta Psi[t_i,k], with m(t) the number of orderings of t; FP64.  j is the output
+ * mode of each computed mode of the block; a mode filled by conjugation gets
+ * P_acc[j'*n + k] += the conjugate of the same sum. */
 int npf_assemble(npf_plan_t plan, int32_t order, int64_t block, const void *h,
                  const void *U, void *P_acc, void *stream);
 
@@ -159,7 +205,8 @@ int npf_assemble(npf_plan_t plan, int32_t order, int64_t block, const void *h,
  * system's work; systems run together in waves whose summed workspace fits the budget
  * (the batching of Alg. 1 applied across systems); the call replays one captured graph.
  * Split-BF16 precision only (problems[s].precision == NPF_BF16X3), N <= 4, n <= 256; every
- * system is one block of all its modes. */
+ * system is one block of all its modes (no mode subset, conjugate pairing or Taylor
+ * convention: NPF_E_UNSUPPORTED). */
 typedef struct npf_batch_s *npf_batch_t;
 
 typedef struct npf_batch_report {

@@ -28,7 +28,9 @@ EXPORTED = [
     "npf_plan_profile", "npf_plan_kernel_times", "npf_error_string", "npf_last_error",
     "npf_hash_fill", "npf_batch_create", "npf_batch_info", "npf_batch_destroy",
     "npf_batch_run", "npf_batch_tune", "npf_batch_launches", "npf_batch_time",
+    "npf_plan_modes",
 ]
+A_DERIVATIVE, A_TAYLOR = 0, 1
 
 
 class NpfError(RuntimeError):
@@ -58,6 +60,10 @@ class NpfProblem(ctypes.Structure):
         ("eps", ctypes.c_double), ("tau", ctypes.c_double), ("delta", ctypes.c_double),
         ("hbm_budget_bytes", ctypes.c_int64), ("block_modes", ctypes.c_int64),
         ("flags", ctypes.c_int32), ("support_max", ctypes.c_int32),
+        ("a_convention", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_modes", ctypes.c_int64), ("modes", ctypes.c_void_p), ("conj_of", ctypes.c_void_p),
+        ("host_U", ctypes.c_void_p), ("host_V", ctypes.c_void_p),
+        ("host_lambda", ctypes.c_void_p), ("check_tol", ctypes.c_double),
     ]
 
 
@@ -71,6 +77,7 @@ class NpfPlanReport(ctypes.Structure):
         ("n_blocks", ctypes.c_int64),
         ("unique_tuples", ctypes.c_int64 * (NPF_MAX_ORDER + 1)),
         ("modal_entries", ctypes.c_int64),
+        ("output_modes", ctypes.c_int64), ("computed_modes", ctypes.c_int64),
     ]
 
 
@@ -99,6 +106,7 @@ def lib():
         P, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         L.npf_plan_create.argtypes = [ctypes.POINTER(NpfProblem), ctypes.POINTER(P)]
         L.npf_plan_info.argtypes = [P, ctypes.POINTER(NpfPlanReport)]
+        L.npf_plan_modes.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.npf_plan_destroy.argtypes = [P]
         L.npf_plan_destroy.restype = None
         L.npf_modal_contract.argtypes = [P, i32, i64, ctypes.POINTER(NpfTensor), P, P, P, i64, P, P]
@@ -132,7 +140,7 @@ def lib():
                   "npf_assemble", "npf_finalize", "npf_run", "npf_plan_profile",
                   "npf_plan_kernel_times", "npf_hash_fill", "npf_batch_create",
                   "npf_batch_info", "npf_batch_run", "npf_batch_tune", "npf_batch_launches",
-                  "npf_batch_time"):
+                  "npf_batch_time", "npf_plan_modes"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -167,14 +175,52 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def conj_pairs(lam) -> np.ndarray:
+    """conj_of for a spectrum whose complex eigenvalues come in exactly conjugate pairs (as
+    for a real system): the mode with the conjugate eigenvalue, itself for a real one."""
+    lam = np.asarray(lam, np.complex128)
+    out = np.arange(len(lam), dtype=np.int64)
+    index = {}
+    for i, v in enumerate(lam):
+        index.setdefault((v.real, v.imag), []).append(i)
+    for i, v in enumerate(lam):
+        if v.imag != 0:
+            cands = index.get((v.real, -v.imag), [])
+            if len(cands) != 1 or len(index[(v.real, v.imag)]) != 1:
+                raise ValueError(f"mode {i} has no unique conjugate partner")
+            out[i] = cands[0]
+    return out
+
+
 class Plan:
-    """Owns an npf_plan_t (host metadata only)."""
+    """Owns an npf_plan_t (host metadata only).
+
+    modes: output modes (None = all); conj_of: mode pairing of a real system (conj_pairs);
+    taylor: A_M holds Taylor coefficients (no 1/M!); check: (U, V, lam) host arrays for the
+    planner's precondition checks (Psi Phi = I, the pairing)."""
 
     def __init__(self, n: int, order_max: int, precision: str = "fp64", eps: float = 1e-9,
                  tau: float = 1e-2, delta: float = 1.0, budget_bytes: int = 0,
-                 block_modes: int = 0, graph: bool = True, support_max: int = 0):
+                 block_modes: int = 0, graph: bool = True, support_max: int = 0,
+                 modes=None, conj_of=None, taylor: bool = False, check=None,
+                 check_tol: float = 0.0):
+        keep = []
+
+        def arr(a, dt):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data_as(ctypes.c_void_p)
+
+        m = None if modes is None else np.asarray(modes, np.int64)
+        hu, hv, hl = (None, None, None) if check is None else check
         prob = NpfProblem(n, order_max, PRECISIONS[precision], eps, tau, delta, budget_bytes,
-                          block_modes, 0 if graph else NPF_FLAG_NO_GRAPH, int(support_max))
+                          block_modes, 0 if graph else NPF_FLAG_NO_GRAPH, int(support_max),
+                          A_TAYLOR if taylor else A_DERIVATIVE, 0,
+                          0 if m is None else len(m), arr(m, np.int64), arr(conj_of, np.int64),
+                          arr(hu, np.complex128), arr(hv, np.complex128), arr(hl, np.complex128),
+                          float(check_tol))
         h = ctypes.c_void_p()
         _check(lib().npf_plan_create(ctypes.byref(prob), ctypes.byref(h)), "npf_plan_create")
         self._h = h
@@ -186,6 +232,16 @@ class Plan:
         self.n_blocks = r.n_blocks
         self.unique_tuples = list(r.unique_tuples)
         self.modal_entries = r.modal_entries
+        self.output_modes = r.output_modes
+        self.computed_modes = r.computed_modes
+
+    def modes(self):
+        """(computed modes in block order, output mode each fills by conjugation or -1)."""
+        nc = self.computed_modes
+        c = (ctypes.c_int64 * max(1, nc))()
+        f = (ctypes.c_int64 * max(1, nc))()
+        _check(lib().npf_plan_modes(self._h, c, f), "npf_plan_modes")
+        return list(c)[:nc], list(f)[:nc]
 
     def close(self):
         if self._h:
@@ -340,20 +396,26 @@ def upload_system(sys, device, sparse: Optional[bool] = None,
 
 def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0,
             block_modes: int = 0, sparse: Optional[bool] = None, graph: bool = True,
-            hash_source: bool = True, support_max: Optional[int] = None):
+            hash_source: bool = True, support_max: Optional[int] = None, modes=None,
+            conj: bool = False, taylor: bool = False, fill=None):
     """Run the fused hot path on one system; returns (NPF, {M: P_M}) as numpy arrays.
     support_max (default: the system's own bound, 0 when its tensors are not sent sparse)
-    selects the lower-indices-first route for sparse orders."""
+    selects the lower-indices-first route for sparse orders.  modes: output modes (None =
+    all); conj: compute one mode of each conjugate pair and fill the other; taylor: the
+    system's A_M hold Taylor coefficients (NPF_A_TAYLOR).  Rows / columns that are not
+    written hold `fill` (default NaN)."""
     import torch
     dev = upload_system(sys, device, sparse, hash_source)
     if support_max is None:
         support_max = sys.support_max if sparse in (None, True) else 0
     plan = Plan(sys.n, sys.order_max, precision, sys.eps, sys.tau, sys.delta, budget_bytes,
-                block_modes, graph, support_max)
+                block_modes, graph, support_max, modes=modes,
+                conj_of=conj_pairs(sys.lam) if conj else None, taylor=taylor)
     ws = plan.workspace(device)
     n, N = sys.n, sys.order_max
-    P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
-    npf = torch.empty((n, n), dtype=torch.complex128, device=device)
+    fv = complex(np.nan, np.nan) if fill is None else fill
+    P = torch.full((N - 1, n, n), fv, dtype=torch.complex128, device=device)
+    npf = torch.full((n, n), fv, dtype=torch.complex128, device=device)
     plan.run(dev.tensors, dev.U, dev.V, dev.lam, ws, P, npf)
     torch.cuda.synchronize(device)
     Ps = {M: P[M - 2].cpu().numpy() for M in range(2, N + 1)}

@@ -68,10 +68,11 @@ void block_range(const npf_plan_s *p, int64_t block, int64_t &b0, int64_t &b1)
     }
 }
 
+// Computed modes [j0, j0 + J) of block b (indices into the plan's computed-mode list).
 void block_modes(const npf_plan_s *p, int64_t b, int64_t &j0, int64_t &J)
 {
     j0 = b * p->J;
-    J = p->n - j0 < p->J ? p->n - j0 : p->J;
+    J = p->nc - j0 < p->J ? p->nc - j0 : p->J;
 }
 
 std::string kname(int M, const char *what, int i = -1)
@@ -103,12 +104,16 @@ int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tenso
 {
     if (tucker) {
         Timed t(p, kname(M, "tucker_psi"), s);
-        return check_hip(launch_tucker_psi(p, M, j0, J, static_cast<const double *>(U),
+        return check_hip(launch_tucker_psi(p, M, j0, J,
+                                           psi_rows(p, static_cast<const double *>(U),
+                                                    static_cast<const char *>(ws)),
                                            static_cast<char *>(ws), s),
                          "upper-index contraction of the per-row tables");
     }
-    ChainArgs a{p, M, j0, J, A, static_cast<const double *>(U), static_cast<const double *>(V),
-                static_cast<char *>(ws), s};
+    // The upper index runs over the computed modes: their staged Psi rows when the plan
+    // selects modes.
+    const double *Urows = psi_rows(p, static_cast<const double *>(U), static_cast<const char *>(ws));
+    ChainArgs a{p, M, j0, J, A, Urows, static_cast<const double *>(V), static_cast<char *>(ws), s};
     int rc;
     {
         Timed t(p, kname(M, "psi_a"), s);
@@ -122,11 +127,13 @@ int run_chain(const npf_plan_s *p, int M, int64_t j0, int64_t J, const npf_tenso
     return rc;
 }
 
-int stage_operands(const npf_plan_s *p, const void *U, const void *V, void *ws, hipStream_t s)
+int stage_operands(const npf_plan_s *p, const void *U, const void *V, const void *lam, void *ws,
+                   hipStream_t s)
 {
     Timed t(p, "prepare", s);
     return check_hip(launch_prepare(p, static_cast<const double *>(U),
-                                    static_cast<const double *>(V), static_cast<char *>(ws), s),
+                                    static_cast<const double *>(V),
+                                    static_cast<const double *>(lam), static_cast<char *>(ws), s),
                      "operand staging");
 }
 
@@ -146,7 +153,7 @@ extern "C" int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block,
     int64_t b0, b1;
     block_range(plan, block, b0, b1);
     const OrderLayout ol(plan, order);
-    rc = stage_operands(plan, U, V, ws, s);
+    rc = stage_operands(plan, U, V, nullptr, ws, s);
     const bool tucker = tucker_supported(plan, A, order);
     if (!rc && tucker) rc = run_rows(plan, order, A, V, ws, s);
     for (int64_t b = b0; b < b1 && rc == NPF_OK; ++b) {
@@ -253,6 +260,7 @@ struct GraphKey {
     npf_tensor A[NPF_MAX_ORDER];
     const void *ptr[7];
     hipStream_t stream;
+    ModeMap modes;               // the computed modes and their conjugate fills
 };
 
 bool same_key(const GraphKey &a, const GraphKey &b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
@@ -316,6 +324,7 @@ extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, cons
     const void *ptrs[7] = {U, V, lambda, ws, P_out, npf_out, reinterpret_cast<const void *>(ws_bytes)};
     std::memcpy(key.ptr, ptrs, sizeof(ptrs));
     key.stream = s;
+    key.modes = mode_map(plan, 0, plan->nc);
     std::lock_guard<std::mutex> lock(g_graph_mu);
     for (auto &e : g_graphs)
         if (same_key(e.key, key)) {
@@ -360,7 +369,7 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
     // Operand staging first on the caller's stream; concurrent runs fork after it (a
     // dependency of the chains on staging work queued on another stream was seen to hold the
     // longest chain behind the other orders' kernels).
-    rc = stage_operands(plan, U, V, ws, s);
+    rc = stage_operands(plan, U, V, lambda, ws, s);
     if (!rc && concurrent) rc = check_hip(hipEventRecord(cs->ev_start, s), "fork");
     auto reduce = [&](int M, int64_t j0, int64_t J, hipStream_t st) {
         const OrderLayout ol(plan, M);
@@ -407,7 +416,7 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
         for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
             const hipStream_t sm = M < plan->N ? cs->side[M] : s;
             if (M > 2) rc = check_hip(hipStreamWaitEvent(sm, cs->ev_done[M - 1], 0), "join");
-            if (!rc) rc = reduce(M, 0, plan->n, sm);
+            if (!rc) rc = reduce(M, 0, plan->nc, sm);
             if (!rc && M < plan->N) rc = check_hip(hipEventRecord(cs->ev_done[M], sm), "join");
         }
     return rc;

@@ -48,8 +48,14 @@ struct GraphEntry {
     std::vector<uintptr_t> key;
     hipGraphExec_t exec = nullptr;
     void *table = nullptr;     // pinned host copy of the argument table this graph uploads
+    hipEvent_t done = nullptr; // recorded after every launch of the graph
     uint64_t used = 0;
 };
+
+// Graphs kept per batch; further argument sets run eagerly (a cached graph is destroyed only
+// with the batch, or when the autotuner changes the launches, and only after its last
+// launch has completed).
+constexpr size_t kMaxBatchGraphs = 4;
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -75,13 +81,28 @@ struct npf_batch_s {
 
 namespace {
 
+// Destroys the cached graphs.  Each one's last launch may still be running (or waiting on
+// its stream); the pinned table its copy node reads and the executable are released only
+// after the event recorded behind that launch has completed.
 void free_graphs(npf_batch_s *b)
 {
     for (auto &g : b->graphs) {
+        if (g.done) {
+            (void)hipEventSynchronize(g.done);
+            (void)hipEventDestroy(g.done);
+        }
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (g.table) (void)hipHostFree(g.table);
     }
     b->graphs.clear();
+}
+
+int launch_graph(GraphEntry &g, hipStream_t st)
+{
+    hipError_t e = hipGraphLaunch(g.exec, st);
+    if (e == hipSuccess) e = hipEventRecord(g.done, st);
+    if (e == hipSuccess) return NPF_OK;
+    return fail(NPF_E_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
 }
 
 // Workgroups per system of a shared launch, in proportion to the work, at least one and at
@@ -153,7 +174,7 @@ int run_waves(npf_batch_s *b, const npf_tensor *A, const void *const *U, const v
         for (int s : ws_sys) {
             const npf_plan_s *p = b->sys[s].plan;
             rc = check_hip(launch_prepare(p, static_cast<const double *>(U[s]),
-                                          static_cast<const double *>(V[s]), region(s), st),
+                                          static_cast<const double *>(V[s]), nullptr, region(s), st),
                            "operand staging");
             if (rc) return rc;
         }
@@ -273,6 +294,8 @@ npf_batch_s::~npf_batch_s()
 {
     free_graphs(this);
     for (auto &s : sys) npf_plan_destroy(s.plan);
+    // The eager staging table is read by a copy that may still be queued.
+    if (table_pending && table_done) (void)hipEventSynchronize(table_done);
     if (table) (void)hipHostFree(table);
     if (table_done) (void)hipEventDestroy(table_done);
 }
@@ -294,6 +317,10 @@ extern "C" int npf_batch_create(const npf_problem *problems, int64_t count, int6
         if (q.order_max > 4 || q.n > 256) {
             delete b;
             return fail(NPF_E_UNSUPPORTED, "batched systems need N <= 4 and n <= 256");
+        }
+        if (q.n_modes != 0 || q.conj_of || q.a_convention != NPF_A_DERIVATIVE) {
+            delete b;
+            return fail(NPF_E_UNSUPPORTED, "batched systems run all modes of derivative tensors");
         }
         q.block_modes = 0;
         q.hbm_budget_bytes = 0;
@@ -440,15 +467,21 @@ extern "C" int npf_batch_run(npf_batch_t b, const npf_tensor *A, const void *con
     for (auto &g : b->graphs)
         if (g.key == key) {
             g.used = ++b->clock;
-            return check_hip(hipGraphLaunch(g.exec, st), "graph launch");
+            return launch_graph(g, st);
         }
+    if (b->graphs.size() >= kMaxBatchGraphs) return run_eager(b, A, U, V, lambda, w, P_out, npf_out, st, nullptr);
     GraphEntry e;
     e.key = std::move(key);
-    if (hipHostMalloc(&e.table, size_t(b->table_bytes), hipHostMallocDefault) != hipSuccess)
+    if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess)
         return run_eager(b, A, U, V, lambda, w, P_out, npf_out, st, nullptr);
+    if (hipHostMalloc(&e.table, size_t(b->table_bytes), hipHostMallocDefault) != hipSuccess) {
+        (void)hipEventDestroy(e.done);
+        return run_eager(b, A, U, V, lambda, w, P_out, npf_out, st, nullptr);
+    }
     fill_table(b, static_cast<char *>(e.table), A, U, V, lambda, w);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipHostFree(e.table);
+        (void)hipEventDestroy(e.done);
         return run_eager(b, A, U, V, lambda, w, P_out, npf_out, st, nullptr);
     }
     rc = check_hip(hipMemcpyAsync(w, e.table, size_t(b->table_bytes), hipMemcpyHostToDevice, st),
@@ -459,25 +492,19 @@ extern "C" int npf_batch_run(npf_batch_t b, const npf_tensor *A, const void *con
     if (rc || ec != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
         (void)hipHostFree(e.table);
+        (void)hipEventDestroy(e.done);
         return rc ? rc : check_hip(ec != hipSuccess ? ec : hipErrorUnknown, "graph capture");
     }
     const hipError_t ei = hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) {
         (void)hipHostFree(e.table);
+        (void)hipEventDestroy(e.done);
         return check_hip(ei, "graph instantiate");
-    }
-    if (b->graphs.size() >= 4) {
-        size_t lru = 0;
-        for (size_t i = 1; i < b->graphs.size(); ++i)
-            if (b->graphs[i].used < b->graphs[lru].used) lru = i;
-        (void)hipGraphExecDestroy(b->graphs[lru].exec);
-        (void)hipHostFree(b->graphs[lru].table);
-        b->graphs.erase(b->graphs.begin() + lru);
     }
     e.used = ++b->clock;
     b->graphs.push_back(e);
-    return check_hip(hipGraphLaunch(e.exec, st), "graph launch");
+    return launch_graph(b->graphs.back(), st);
 }
 
 extern "C" int npf_batch_tune(npf_batch_t b, const npf_tensor *A, const void *const *U,

@@ -25,6 +25,7 @@ struct Bf3Args {
     const __bf16 *zetaE;     // 6 planes [pl][t/4][k][t%4]
     const float2 *zeta32;    // [npad][npad] delta Psi
     const double2 *lam;      // [n]
+    const double2 *lamj;     // fused: eigenvalues of the computed modes (mode j0 + jl)
     const uint64_t *ptab;    // sorted prefixes (fused: length M-1; stage: length i-1)
     const uint64_t *stab;    // stage: sorted suffixes of length M-i
     double2 *parts;          // fused: [gridDim.x][Jpad][n]
@@ -113,6 +114,7 @@ inline Bf3Args base_args(const npf_plan_s *p, char *ws, const double *lam)
     a.zetaE = reinterpret_cast<const __bf16 *>(base + 34 * N2);
     a.zeta32 = reinterpret_cast<const float2 *>(base + 50 * N2);
     a.lam = reinterpret_cast<const double2 *>(lam);
+    a.lamj = a.lam;
     a.n = p->n;
     a.Jpad = p->Jpad;
     a.eps = p->prob.eps;
@@ -144,6 +146,7 @@ inline Bf3Args fused_args(const npf_plan_s *p, int M, int64_t j0, int64_t J, con
                           char *ws)
 {
     Bf3Args a = base_args(p, ws, lam);
+    a.lamj = reinterpret_cast<const double2 *>(lam_rows(p, lam, ws));
     a.X = ws + p->lay.buf[(M - 1) % 2];
     a.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
     a.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);

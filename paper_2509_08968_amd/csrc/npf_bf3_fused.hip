@@ -36,7 +36,7 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
     const bool wave_on = jw < a.Jpad;
     const int64_t jl = jw + c;
     const bool j_ok = wave_on && jl < a.J;
-    const double2 lam_j = j_ok ? Llam[a.j0 + jl] : make_double2(0.0, 0.0);
+    const double2 lam_j = j_ok ? a.lamj[a.j0 + jl] : make_double2(0.0, 0.0);
     // Below this |D|^2 (FP32) the divisor is finished in FP64: the tau band, and a margin
     // around eps so that the clamp is decided in FP64 exactly as specified.
     const float guard = fmaxf(float(a.tau2), float(4.0 * a.eps * a.eps));

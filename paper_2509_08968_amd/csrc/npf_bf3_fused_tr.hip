@@ -66,7 +66,7 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
     const bool wave_on = jw < a.Jpad && islot < IPW;
     const int64_t jl = jw + c;
     const bool j_ok = wave_on && jl < a.J;
-    const double2 lam_j = j_ok ? Llam[a.j0 + jl] : make_double2(0.0, 0.0);
+    const double2 lam_j = j_ok ? a.lamj[a.j0 + jl] : make_double2(0.0, 0.0);
     const float guard = fmaxf(float(a.tau2), float(4.0 * a.eps * a.eps));
     const int nn = int(a.n), jp = int(a.Jpad);
     const int64_t istride = int64_t(bp.gx) * IPW;

@@ -27,16 +27,30 @@ constexpr int64_t kResidentBytes = 128 * 1024;   // LDS budget for resident oper
 //   BF3: phi as 6 BF16 planes (re h/m/l, im h/m/l) in layout [pl][a/8][t][a%8],
 //        zeta as 6 planes (re h/m/l, im h/m/l) in the fragment order of zeta_frag_index.
 // Also the tables of sorted tuples of length 1..N-1 (8 bits per entry), in colex order.
+// With selected modes, also the Psi rows and (when lam is given) the eigenvalues of the
+// computed modes: msel[c*n + k] = Psi[row[c], k] and msel[nc*n + c] = lam[row[c]].
 __global__ void __launch_bounds__(256)
 prepare(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta, int64_t n,
         int64_t npad, int eng, double2 *__restrict__ zeta64, void *__restrict__ phiE,
         void *__restrict__ zetaE, float2 *__restrict__ zeta32, uint64_t *__restrict__ ttab,
-        TupleTables tt)
+        TupleTables tt, const double2 *__restrict__ lam, double2 *__restrict__ msel, int64_t nc,
+        ModeMap mm)
 {
     const int64_t N2 = npad * npad;
-    const int64_t total = N2 + tt.total;
+    const int64_t nsel = msel ? nc * (n + 1) : 0;
+    const int64_t total = N2 + tt.total + nsel;
     for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < total;
          x += int64_t(gridDim.x) * blockDim.x) {
+        if (x >= N2 + tt.total) {
+            const int64_t y = x - N2 - tt.total;
+            if (y < nc * n) {
+                const int64_t c = y / n, k = y - c * n;
+                msel[y] = Psi[int64_t(mm.row[c]) * n + k];
+            } else if (lam) {
+                msel[y] = lam[mm.row[y - nc * n]];
+            }
+            continue;
+        }
         if (x >= N2) {
             int64_t y = x - N2;
             int m = 1;
@@ -113,6 +127,7 @@ struct FusedArgs {
     const void *zetaE;       // staged zeta (engine layout)
     const double2 *zeta64;   // [npad][npad] delta Psi
     const double2 *lam;      // [n]
+    const double2 *lamj;     // eigenvalues of the computed modes (mode j0 + jl)
     const uint64_t *ptab;    // sorted (M-1)-tuples, packed
     double2 *parts;          // [gridDim.x][Jpad][n]
     int64_t n, npad, Jpad, J, j0, items;
@@ -144,7 +159,7 @@ fused_last(FusedArgs a)
     const bool wave_on = jw < a.Jpad;
     const int64_t jl = jw + c;                                   // this lane's mode (block-local)
     const bool j_ok = wave_on && jl < a.J;
-    const double2 lam_j = j_ok ? a.lam[a.j0 + jl] : make_double2(0.0, 0.0);
+    const double2 lam_j = j_ok ? a.lamj[a.j0 + jl] : make_double2(0.0, 0.0);
     const int kt0 = blockIdx.z * NKTW;
     const int nkt = int(a.npad / 16);
     constexpr int TC = T::TC;
@@ -398,11 +413,14 @@ fused_last(FusedArgs a)
 // For the last order (npf non-null) the finished sum over orders also gives the NPF entry
 // NPF[k, j] = Phi[k, j] (delta Psi[j, k] + psum[j, k]) of Alg. 2 step 20 (the arithmetic of
 // finalize_simt).
+// Rows: partial row jj (computed mode j0 + jj) is output mode mm.row[jj]; a mode filled by
+// conjugation (mm.conj[jj]) gets the conjugate P, sum and NPF entries.  scale multiplies P
+// (1, or M! for Taylor-coefficient input).
 __global__ void __launch_bounds__(256)
 reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, int64_t J,
-             int64_t n, int64_t j0, double2 *__restrict__ P, double2 *__restrict__ psum, int first,
-             const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta,
-             double2 *__restrict__ npf)
+             int64_t n, ModeMap mm, double scale, double2 *__restrict__ P,
+             double2 *__restrict__ psum, int first, const double2 *__restrict__ Phi,
+             const double2 *__restrict__ Psi, double delta, double2 *__restrict__ npf)
 {
     __shared__ double2 part[16][16];
     const int64_t per = J * n;
@@ -435,19 +453,34 @@ reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, in
                 tr += part[q][el].x;
                 ti += part[q][el].y;
             }
-            P[j0 * n + e] = make_double2(tr, ti);
+            tr *= scale;
+            ti *= scale;
+            const int64_t jj = e / n, k = e - jj * n;
+            const int64_t j = mm.row[jj];
+            P[j * n + k] = make_double2(tr, ti);
             double2 tot = make_double2(tr, ti);
             if (!first) {
-                const double2 o = psum[j0 * n + e];
+                const double2 o = psum[j * n + k];
                 tot = make_double2(o.x + tr, o.y + ti);
             }
-            psum[j0 * n + e] = tot;
+            psum[j * n + k] = tot;
             if (npf) {
-                const int64_t j = j0 + e / n, k = e % n;
                 const double2 w = Psi[j * n + k];
                 double2 z = make_double2(delta * w.x, delta * w.y);
                 z = add_fp64(z, tot);
                 npf[k * n + j] = cmul(Phi[k * n + j], z);
+            }
+            if (mm.conj[jj] != kNoRow) {
+                const int64_t jc = mm.conj[jj];
+                const double2 totc = make_double2(tot.x, -tot.y);
+                P[jc * n + k] = make_double2(tr, -ti);
+                psum[jc * n + k] = totc;
+                if (npf) {
+                    const double2 w = Psi[jc * n + k];
+                    double2 z = make_double2(delta * w.x, delta * w.y);
+                    z = add_fp64(z, totc);
+                    npf[k * n + jc] = cmul(Phi[k * n + jc], z);
+                }
             }
         }
         __syncthreads();
@@ -521,19 +554,23 @@ int64_t fused_max_slots(const npf_plan_s *p, int64_t Jpad)
     return fused_gx(p, -1, Jpad) * (bf3_tr_fused_supported(p) ? fused_bf3_tr_slices(p, Jpad) : 1);
 }
 
-hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V, char *ws,
-                          hipStream_t s)
+hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V,
+                          const double *lam, char *ws, hipStream_t s)
 {
     const int64_t N2 = p->npad * p->npad;
     char *base = ws + p->lay.phi;
-    const int64_t work = N2 + p->tt.total;
+    const bool sel = p->select;
+    const int64_t work = N2 + p->tt.total + (sel ? p->nc * (p->n + 1) : 0);
     int64_t blocks = (work + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(prepare, dim3(unsigned(blocks)), dim3(256), 0, s,
                        reinterpret_cast<const double2 *>(V), reinterpret_cast<const double2 *>(U),
                        p->prob.delta, p->n, p->npad, p->prec, reinterpret_cast<double2 *>(base),
                        base + 16 * N2, base + 34 * N2, reinterpret_cast<float2 *>(base + 50 * N2),
-                       reinterpret_cast<uint64_t *>(ws + p->lay.ttab), p->tt);
+                       reinterpret_cast<uint64_t *>(ws + p->lay.ttab), p->tt,
+                       reinterpret_cast<const double2 *>(lam),
+                       sel ? reinterpret_cast<double2 *>(ws + p->lay.msel) : nullptr, p->nc,
+                       sel ? mode_map(p, 0, p->nc) : ModeMap{});
     return hipGetLastError();
 }
 
@@ -548,6 +585,7 @@ hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, 
     fa.zetaE = base + 34 * N2;
     fa.zeta64 = reinterpret_cast<const double2 *>(base);
     fa.lam = reinterpret_cast<const double2 *>(lam);
+    fa.lamj = reinterpret_cast<const double2 *>(lam_rows(p, lam, ws));
     fa.ptab = reinterpret_cast<const uint64_t *>(ws + p->lay.ttab) + p->tt.off[M - 1];
     fa.parts = reinterpret_cast<double2 *>(ws + p->lay.parts);
     fa.n = p->n;
@@ -577,20 +615,22 @@ hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J
                                double *psum, bool first, char *ws, hipStream_t s,
                                const NpfOut *fin)
 {
-    return launch_reduce_parts_n(p, fused_groups(p, M), j0, J, P, psum, first, ws, s, fin);
+    return launch_reduce_parts_n(p, fused_groups(p, M), j0, J, P, psum, first, ws, s, fin,
+                                 p->a_scale[M]);
 }
 
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
                                  double *P, double *psum, bool first, char *ws, hipStream_t s,
-                                 const NpfOut *fin)
+                                 const NpfOut *fin, double scale)
 {
     const int64_t per = J * p->n;
     int64_t wg = (per + 15) / 16;
     if (wg > 8192) wg = 8192;
     hipLaunchKernelGGL(reduce_parts, dim3(unsigned(wg)), dim3(256), 0, s,
                        reinterpret_cast<const double2 *>(ws + p->lay.parts), nparts, p->Jpad, J,
-                       p->n, j0, reinterpret_cast<double2 *>(P), reinterpret_cast<double2 *>(psum),
-                       first ? 1 : 0, fin ? reinterpret_cast<const double2 *>(fin->V) : nullptr,
+                       p->n, mode_map(p, j0, J), scale, reinterpret_cast<double2 *>(P),
+                       reinterpret_cast<double2 *>(psum), first ? 1 : 0,
+                       fin ? reinterpret_cast<const double2 *>(fin->V) : nullptr,
                        fin ? reinterpret_cast<const double2 *>(fin->U) : nullptr, p->prob.delta,
                        fin ? reinterpret_cast<double2 *>(fin->npf) : nullptr);
     return hipGetLastError();

@@ -33,6 +33,9 @@ struct TupleTables {
     int maxlen = 0;
 };
 
+// Highest order the FP32 and split-BF16 paths serve (they meet their 1e-6 bound there).
+constexpr int kMixedMaxOrder = 4;
+
 // Largest per-row support of the lower-indices-first route for sparse tensors.
 constexpr int kTuckerMaxSupport = 8;
 
@@ -54,7 +57,21 @@ struct Layout {
     int64_t parts = 0;           // per-workgroup partial P of the fused kernel
     int64_t parts_bytes = 0;
     TuckerLayout tk;
+    int64_t msel = 0;            // Psi rows [nc][n] and eigenvalues [nc] of the computed
+                                 // modes (c128), when the plan selects modes
     int64_t total = 0;
+};
+
+// Largest number of output modes of one call (n <= 256 for the MFMA kernels).
+constexpr int kMaxModes = 256;
+constexpr uint16_t kNoRow = 0xFFFF;
+
+// Output rows of the computed modes c0 .. c0 + J - 1 (passed by value to the kernels that
+// write P rows or read one eigenvalue per mode): row[jj] is the output mode of computed mode
+// c0 + jj, conj[jj] the output mode filled with its conjugate (kNoRow: none).
+struct ModeMap {
+    uint16_t row[kMaxModes];
+    uint16_t conj[kMaxModes];
 };
 
 }  // namespace npf
@@ -95,6 +112,15 @@ struct npf_plan_s {
     // (one set per device), not to the plan.
     bool concurrent = false;
     npf::Layout ord[NPF_MAX_ORDER + 1];
+    // Computed modes in block order (cm) and the output mode each fills by conjugation (cj,
+    // -1 for none); nc = cm.size().  `select` is true unless cm = 0..n-1 with no fills, and
+    // then the Psi rows and eigenvalues of the computed modes are staged in the workspace.
+    int64_t nc = 0;
+    std::vector<int32_t> cm, cj;
+    int64_t n_out = 0;                   // output modes (computed + filled)
+    bool select = false;
+    // Factor applied to every P_M (and staged C): 1, or M! for Taylor-coefficient input.
+    double a_scale[NPF_MAX_ORDER + 1] = {1, 1, 1, 1, 1, 1, 1};
 };
 
 namespace npf {
@@ -168,8 +194,14 @@ hipError_t launch_finalize(const npf_plan_s *p, const double *U, const double *V
                            const double *P_sum, double *npf_out, hipStream_t s);
 // Operand copies for the MFMA kernels (zero padded, in the plan's precision) and the
 // tuple tables.
-hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V, char *ws,
-                          hipStream_t s);
+hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V,
+                          const double *lam, char *ws, hipStream_t s);
+// Output rows of computed modes [c0, c0 + J).
+ModeMap mode_map(const npf_plan_s *p, int64_t c0, int64_t J);
+// Psi rows and eigenvalue of the computed modes: the staged copies when the plan selects
+// modes, else the caller's arrays.
+const double *psi_rows(const npf_plan_s *p, const double *U, const char *ws);
+const double *lam_rows(const npf_plan_s *p, const double *lam, const char *ws);
 // Fused last mode product + divisor + division + reduction: per-workgroup partial P.
 hipError_t launch_fused_last(const npf_plan_s *p, int M, int64_t j0, int64_t J, const double *lam,
                              char *ws, hipStream_t s);
@@ -212,7 +244,7 @@ int stage_bf3_tr_tiles(int64_t npad);
 // Partial sums of a block's fused-kernel slots (nparts of them) into P rows and psum.
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
                                  double *P, double *psum, bool first, char *ws, hipStream_t s,
-                                 const NpfOut *fin = nullptr);
+                                 const NpfOut *fin = nullptr, double scale = 1.0);
 int64_t fused_default_groups(const npf_plan_s *p, int M);
 bool bf3_tr_fused_supported(const npf_plan_s *p);
 int bf3_items_per_group(int64_t Jpad);

@@ -151,7 +151,7 @@ stage_simt(const Cin *__restrict__ in, Cout *__restrict__ out, const double2 *__
 // ---------------------------------------------------------------- divisor and division
 __global__ void __launch_bounds__(kThreads)
 normal_form_simt(double2 *__restrict__ C, const double2 *__restrict__ lam, int64_t n, int M,
-                 int64_t j0, int64_t J, int64_t UM, double eps)
+                 ModeMap mm, int64_t J, int64_t UM, double eps)
 {
     const int64_t total = J * UM;
     int32_t t[kMaxOrder];
@@ -161,16 +161,17 @@ normal_form_simt(double2 *__restrict__ C, const double2 *__restrict__ lam, int64
         colex_unrank(r, M, n, t);
         double2 acc = lam[t[0]];
         for (int l = 1; l < M; ++l) acc = add_fp64(acc, lam[t[l]]);
-        const double2 d = divisor_fp64(acc, lam[j0 + jj], eps);
+        const double2 d = divisor_fp64(acc, lam[mm.row[jj]], eps);
         C[x] = cdiv(C[x], d);
     }
 }
 
 // ---------------------------------------------------------------- reduction to P
-// One thread per (mode j, state k): sequential sum over sorted tuples in colex order.
+// One thread per (mode j, state k): sequential sum over sorted tuples in colex order; the
+// row of block mode jj is output mode mm.row[jj], and mm.conj[jj] gets the conjugate.
 __global__ void __launch_bounds__(kThreads)
 assemble_simt(const double2 *__restrict__ h, const double2 *__restrict__ Psi, int64_t n, int M,
-              int64_t j0, int64_t J, int64_t UM, double delta, double2 *__restrict__ P)
+              ModeMap mm, int64_t J, int64_t UM, double delta, double2 *__restrict__ P)
 {
     const int64_t total = J * n;
     int32_t t[kMaxOrder];
@@ -194,8 +195,12 @@ assemble_simt(const double2 *__restrict__ h, const double2 *__restrict__ Psi, in
             si += m * hz.y;
             ++r;
         } while (colex_next(t, M, n));
-        double2 *dst = P + (j0 + jj) * n + k;
+        double2 *dst = P + int64_t(mm.row[jj]) * n + k;
         *dst = make_double2(dst->x - sr, dst->y - si);
+        if (mm.conj[jj] != kNoRow) {
+            double2 *dc = P + int64_t(mm.conj[jj]) * n + k;
+            *dc = make_double2(dc->x - sr, dc->y + si);
+        }
     }
 }
 
@@ -341,12 +346,12 @@ hipError_t launch_last_to_c(const ChainArgs &a, double *C_out)
         hipLaunchKernelGGL((stage_simt<double2, double2, double, true>), dim3(grid),
                            dim3(kThreads), shm, a.stream, reinterpret_cast<const double2 *>(src),
                            reinterpret_cast<double2 *>(C_out), Phi, p.n, M, i, U_prev, U_suf,
-                           U_in, a.J, p.Jpad, p.U[M], 1.0 / fact, items);
+                           U_in, a.J, p.Jpad, p.U[M], p.a_scale[M] / fact, items);
     else
         hipLaunchKernelGGL((stage_simt<float2, double2, float, true>), dim3(grid), dim3(kThreads),
                            shm, a.stream, reinterpret_cast<const float2 *>(src),
                            reinterpret_cast<double2 *>(C_out), Phi, p.n, M, i, U_prev, U_suf,
-                           U_in, a.J, p.Jpad, p.U[M], 1.0 / fact, items);
+                           U_in, a.J, p.Jpad, p.U[M], p.a_scale[M] / fact, items);
     return hipGetLastError();
 }
 
@@ -356,7 +361,7 @@ hipError_t launch_normal_form(const npf_plan_s *p, int M, int64_t j0, int64_t J,
     const int64_t total = J * p->U[M];
     hipLaunchKernelGGL(normal_form_simt, dim3(grid_for(total)), dim3(kThreads), 0, s,
                        reinterpret_cast<double2 *>(C), reinterpret_cast<const double2 *>(lam),
-                       p->n, M, j0, J, p->U[M], p->prob.eps);
+                       p->n, M, mode_map(p, j0, J), J, p->U[M], p->prob.eps);
     return hipGetLastError();
 }
 
@@ -366,7 +371,8 @@ hipError_t launch_assemble(const npf_plan_s *p, int M, int64_t j0, int64_t J, co
     const int64_t total = J * p->n;
     hipLaunchKernelGGL(assemble_simt, dim3(grid_for(total)), dim3(kThreads), 0, s,
                        reinterpret_cast<const double2 *>(h), reinterpret_cast<const double2 *>(U),
-                       p->n, M, j0, J, p->U[M], p->prob.delta, reinterpret_cast<double2 *>(P_acc));
+                       p->n, M, mode_map(p, j0, J), J, p->U[M], p->prob.delta,
+                       reinterpret_cast<double2 *>(P_acc));
     return hipGetLastError();
 }
 

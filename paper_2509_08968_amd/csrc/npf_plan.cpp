@@ -2,6 +2,7 @@
 // budget (the batch-size rule of Alg. 1), the workspace layout, and Alg. 1 itself.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 
@@ -55,6 +56,7 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     L.pm = take(p.n * p.n * 16);
     L.phi_bytes = p.npad * p.npad * 16 * 4;
     L.phi = take(L.phi_bytes);
+    if (p.select) L.msel = take(p.nc * (p.n + 1) * 16);
     const int64_t nparts = std::max<int64_t>(1, fused_max_slots(&p, Jpad));
     L.parts_bytes = nparts * Jpad * p.n * 16;
     L.parts = take(L.parts_bytes);
@@ -90,6 +92,7 @@ static Layout make_split_layout(const npf_plan_s &p, int64_t Jpad, Layout *ord)
     C.psum = take(p.n * p.n * 16);
     C.phi_bytes = p.npad * p.npad * 16 * 4;
     C.phi = take(C.phi_bytes);
+    if (p.select) C.msel = take(p.nc * (p.n + 1) * 16);
     const int64_t nparts = std::max<int64_t>(1, fused_max_slots(&p, Jpad));
     const int smax = p.prob.support_max;
     for (int M = 2; M <= p.N; ++M) {
@@ -121,6 +124,108 @@ static Layout make_split_layout(const npf_plan_s &p, int64_t Jpad, Layout *ord)
     return R;
 }
 
+// Output modes, conjugate pairs and the preconditions with host copies (Alg. 2 needs
+// Psi Phi = I; the pairing of conj_of must hold for the filled modes to be right).
+static int check_modes(const npf_problem &q, std::vector<int32_t> &cm, std::vector<int32_t> &cj,
+                       int64_t &n_out)
+{
+    const int64_t n = q.n;
+    std::vector<char> out(size_t(n), q.n_modes == 0 ? 1 : 0);
+    if (q.n_modes < 0 || q.n_modes > n) return fail(NPF_E_INVALID, "n_modes outside [0, n]");
+    if (q.n_modes > 0) {
+        if (!q.modes) return fail(NPF_E_INVALID, "n_modes > 0 with a null mode list");
+        for (int64_t i = 0; i < q.n_modes; ++i) {
+            const int64_t j = q.modes[i];
+            if (j < 0 || j >= n) return fail(NPF_E_INVALID, "output mode outside [0, n)");
+            if (out[size_t(j)]) return fail(NPF_E_INVALID, "output mode listed twice");
+            out[size_t(j)] = 1;
+        }
+    }
+    if (q.conj_of)
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t c = q.conj_of[i];
+            if (c < 0 || c >= n || q.conj_of[c] != i)
+                return fail(NPF_E_INVALID, "conj_of is not an involution on [0, n)");
+        }
+    cm.clear();
+    cj.clear();
+    n_out = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!out[size_t(i)]) continue;
+        ++n_out;
+        const int64_t c = q.conj_of ? q.conj_of[i] : i;
+        if (c != i && out[size_t(c)]) {
+            if (c < i) continue;                       // filled from its partner c
+            cm.push_back(int32_t(i));
+            cj.push_back(int32_t(c));
+        } else {
+            cm.push_back(int32_t(i));
+            cj.push_back(-1);
+        }
+    }
+    return NPF_OK;
+}
+
+static int check_host_copies(const npf_problem &q)
+{
+    const double tol = q.check_tol > 0.0 ? q.check_tol : 1e-8;
+    const int64_t n = q.n;
+    using cd = std::complex<double>;
+    const cd *U = static_cast<const cd *>(q.host_U);
+    const cd *V = static_cast<const cd *>(q.host_V);
+    const cd *lam = static_cast<const cd *>(q.host_lambda);
+    if (U && V)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                cd s = 0.0;
+                for (int64_t k = 0; k < n; ++k) s += U[i * n + k] * V[k * n + j];
+                if (std::abs(s - (i == j ? cd(1.0) : cd(0.0))) > tol)
+                    return fail(NPF_E_INVALID, "Psi Phi differs from the identity by more than check_tol");
+            }
+    if (!q.conj_of) return NPF_OK;
+    auto maxabs = [n](const cd *x, int64_t count) {
+        double m = 0.0;
+        for (int64_t e = 0; e < count; ++e) m = std::max(m, std::abs(x[e]));
+        return m > 0.0 ? m : 1.0;
+    };
+    const double sl = lam ? maxabs(lam, n) : 1.0, su = U ? maxabs(U, n * n) : 1.0,
+                 sv = V ? maxabs(V, n * n) : 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t c = q.conj_of[i];
+        if (lam && std::abs(lam[c] - std::conj(lam[i])) > tol * sl)
+            return fail(NPF_E_INVALID, "conj_of pairs eigenvalues that are not conjugate");
+        for (int64_t k = 0; k < n; ++k) {
+            if (V && std::abs(V[k * n + c] - std::conj(V[k * n + i])) > tol * sv)
+                return fail(NPF_E_INVALID, "conj_of pairs right eigenvectors that are not conjugate");
+            if (U && std::abs(U[c * n + k] - std::conj(U[i * n + k])) > tol * su)
+                return fail(NPF_E_INVALID, "conj_of pairs left eigenvectors that are not conjugate");
+        }
+    }
+    return NPF_OK;
+}
+
+ModeMap mode_map(const npf_plan_s *p, int64_t c0, int64_t J)
+{
+    ModeMap m;
+    for (int q = 0; q < kMaxModes; ++q) {
+        const int64_t c = c0 + q;
+        const bool in = q < J && c < p->nc;
+        m.row[q] = in ? uint16_t(p->cm[size_t(c)]) : kNoRow;
+        m.conj[q] = (in && p->cj[size_t(c)] >= 0) ? uint16_t(p->cj[size_t(c)]) : kNoRow;
+    }
+    return m;
+}
+
+const double *psi_rows(const npf_plan_s *p, const double *U, const char *ws)
+{
+    return p->select ? reinterpret_cast<const double *>(ws + p->lay.msel) : U;
+}
+
+const double *lam_rows(const npf_plan_s *p, const double *lam, const char *ws)
+{
+    return p->select ? reinterpret_cast<const double *>(ws + p->lay.msel) + 2 * p->nc * p->n : lam;
+}
+
 }  // namespace npf
 
 using namespace npf;
@@ -141,11 +246,41 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
     if (q.hbm_budget_bytes < 0 || q.block_modes < 0)
         return fail(NPF_E_INVALID, "negative budget or block size");
     if (q.support_max < 0) return fail(NPF_E_INVALID, "negative support bound");
+    if (q.a_convention != NPF_A_DERIVATIVE && q.a_convention != NPF_A_TAYLOR)
+        return fail(NPF_E_INVALID, "unknown derivative-tensor convention");
+    if (!(q.check_tol >= 0.0) || !std::isfinite(q.check_tol))
+        return fail(NPF_E_INVALID, "check_tol must be >= 0");
     if (q.n > 256) return fail(NPF_E_UNSUPPORTED, "n > 256 is not supported by the MFMA kernels");
+    // The mixed paths store C once per sorted tuple in FP32, and every ordering of the tuple
+    // reuses that one rounding; beyond order 4 (m(t) up to 120 orderings) the coherent error
+    // exceeds the 1e-6 bound of these paths, so orders 5 and 6 are served in FP64 only.
+    if (q.precision != NPF_FP64 && q.order_max > kMixedMaxOrder)
+        return fail(NPF_E_UNSUPPORTED, "FP32 and split-BF16 plans serve orders up to 4; use FP64 for orders 5-6");
+
+    std::vector<int32_t> cm, cj;
+    int64_t n_out = 0;
+    int rc = check_modes(q, cm, cj, n_out);
+    if (rc) return rc;
+    if ((q.host_U || q.host_V || q.host_lambda) && (rc = check_host_copies(q))) return rc;
 
     npf_plan_s *p = new (std::nothrow) npf_plan_s();
     if (!p) return fail(NPF_E_INVALID, "out of host memory");
     p->prob = q;
+    // The plan keeps its own copies; no caller pointer outlives the call.
+    p->prob.modes = nullptr;
+    p->prob.conj_of = nullptr;
+    p->prob.host_U = p->prob.host_V = p->prob.host_lambda = nullptr;
+    p->cm = std::move(cm);
+    p->cj = std::move(cj);
+    p->nc = int64_t(p->cm.size());
+    p->n_out = n_out;
+    p->select = p->nc != q.n;
+    for (int64_t c = 0; c < p->nc && !p->select; ++c) p->select = p->cm[size_t(c)] != c || p->cj[size_t(c)] >= 0;
+    double fact = 1.0;
+    for (int M = 2; M <= NPF_MAX_ORDER; ++M) {
+        fact *= M;
+        p->a_scale[M] = q.a_convention == NPF_A_TAYLOR ? fact : 1.0;
+    }
     p->n = q.n;
     p->N = q.order_max;
     p->prec = q.precision;
@@ -164,10 +299,11 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
         p->tt.off[m] = p->tt.total;
         p->tt.total += p->U[m];
     }
-    // Block size over output modes: shrink the outermost (mode) dimension until the
+    // Block size over the computed modes: shrink the outermost (mode) dimension until the
     // working set fits the limit, then balance the blocks -- Alg. 1 steps 6-15 applied to
     // this path's working set.
-    const int64_t full = round_up(q.n, 16);
+    const int64_t nc = std::max<int64_t>(p->nc, 1);
+    const int64_t full = round_up(nc, 16);
     int64_t Jpad = full;
     if (q.block_modes > 0) Jpad = std::min(full, round_up(q.block_modes, 16));
     if (q.hbm_budget_bytes > 0) {
@@ -177,8 +313,8 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
             return fail(NPF_E_BUDGET, "memory budget below the smallest block (16 modes)");
         }
     }
-    p->n_blocks = (q.n + Jpad - 1) / Jpad;
-    p->J = (q.n + p->n_blocks - 1) / p->n_blocks;
+    p->n_blocks = (nc + Jpad - 1) / Jpad;
+    p->J = (nc + p->n_blocks - 1) / p->n_blocks;
     p->Jpad = round_up(p->J, 16);
     p->lay = make_layout(*p, p->Jpad);
     for (int M = 0; M <= NPF_MAX_ORDER; ++M) p->ord[M] = p->lay;
@@ -211,6 +347,18 @@ extern "C" int npf_plan_info(npf_plan_t plan, npf_plan_report *r)
         if (m >= 2) entries += plan->n * plan->U[m];
     }
     r->modal_entries = entries;
+    r->output_modes = plan->n_out;
+    r->computed_modes = plan->nc;
+    return NPF_OK;
+}
+
+extern "C" int npf_plan_modes(npf_plan_t plan, int64_t *computed, int64_t *filled)
+{
+    if (!plan) return fail(NPF_E_INVALID, "npf_plan_modes: null plan");
+    for (int64_t c = 0; c < plan->nc; ++c) {
+        if (computed) computed[c] = plan->cm[size_t(c)];
+        if (filled) filled[c] = plan->cj[size_t(c)];
+    }
     return NPF_OK;
 }
 

@@ -96,9 +96,12 @@ class System:
         return max(self.A) if self.A else 1
 
 
+MAX_DRAWS = 1000    # redraws of a spectrum before a generator gives up
+
+
 def _spectrum(n: int, rng: np.random.Generator, min_gap: float = 1e-3) -> np.ndarray:
     """Conjugate pairs: Re ~ U[-2, -0.05], Im ~ U[0.5, 10]; an odd n gets one real root."""
-    while True:
+    for _ in range(MAX_DRAWS):
         lam = np.empty(n, dtype=np.complex128)
         for m in range(n // 2):
             re = rng.uniform(-2.0, -0.05)
@@ -109,6 +112,7 @@ def _spectrum(n: int, rng: np.random.Generator, min_gap: float = 1e-3) -> np.nda
             lam[n - 1] = complex(rng.uniform(-2.0, -0.05), 0.0)
         if _min_gap(lam) >= min_gap:
             return lam
+    raise ValueError(f"no spectrum of {n} eigenvalues at least {min_gap} apart in {MAX_DRAWS} draws")
 
 
 def _min_gap(lam: np.ndarray) -> float:
@@ -209,7 +213,7 @@ def resonant_system(n: int, orders, seed: int, n_res2: int = 4, n_res3: int = 4,
     if n_t + 2 * n_res2 + 3 * n_res3 > n // 2:
         raise ValueError("not enough conjugate pairs for distinct targets and sources")
     rng = np.random.default_rng(seed)
-    while True:
+    for _ in range(MAX_DRAWS):
         lam = _spectrum(n, rng)
         pairs = rng.permutation(n // 2)
         targets, sources = pairs[:n_t], list(pairs[n_t:])
@@ -225,9 +229,61 @@ def resonant_system(n: int, orders, seed: int, n_res2: int = 4, n_res3: int = 4,
             lam[2 * m + 1] = np.conj(val)
         if _min_gap(lam) >= 1e-3 and np.all(np.abs(lam.imag) > 0):
             break
+    else:
+        raise ValueError(f"no resonant spectrum with distinct eigenvalues in {MAX_DRAWS} draws")
     V = _eigvecs(n, rng)
     A = {M: dense_tensor(n, M, float(n) ** (-M / 2.0), rng) for M in orders if M >= 2}
     return _finish(name, n, lam, V, A, {M: None for M in A}, **kw)
+
+
+CLAMP_EPS = 2.0 ** -17          # the clamp threshold of the clamp systems (about 7.6e-6)
+
+
+def clamp_system(n: int, orders, seed: int, eps: float = CLAMP_EPS, name: str = "clamp",
+                 **kw) -> System:
+    """Dense system whose small divisors sit exactly at, just below and just above the clamp
+    threshold ``eps`` of Alg. 2 step 9, with every divisor exact in FP64.
+
+    Eigenvalues are conjugate pairs on the dyadic grid 2^-6 (Re in [-2, -0.0625], Im in
+    [0.5, 10]).  Four target pairs are then set, from distinct non-target sources, to
+        lam_j = lam_p + lam_q                 (order-2 divisor exactly 0: clamped),
+        lam_j = lam_p + lam_q + lam_r         (order-3 divisor exactly 0: clamped),
+        lam_j = lam_p + lam_q - (15/16) eps   (|D| just below eps: clamped),
+        lam_j = lam_p + lam_q - (17/16) eps   (|D| just above eps: not clamped),
+    and, when order 4 is present, a fifth to lam_p + lam_q + lam_r + lam_s (order-4 divisor
+    exactly 0); the conjugate partner follows.  These values need at most 27 significant bits, so
+    the sums of up to four eigenvalues and the divisors are exact in FP64 whatever the
+    summation order.  A_M entries are N(0, 1) / n^(M/2), eps is the system's clamp."""
+    o4 = 4 in orders
+    if n // 2 < (18 if o4 else 13):
+        raise ValueError("clamp systems need 13 conjugate pairs (18 with order 4)")
+    rng = np.random.default_rng(seed)
+    grid = 2.0 ** -6
+    for _ in range(MAX_DRAWS):
+        lam = np.empty(n, dtype=np.complex128)
+        for m in range(n // 2):
+            v = complex(-grid * rng.integers(4, 129), grid * rng.integers(32, 641))
+            lam[2 * m], lam[2 * m + 1] = v, np.conj(v)
+        if n % 2:
+            lam[n - 1] = complex(-grid * rng.integers(4, 129), 0.0)
+        pairs = rng.permutation(n // 2)
+        nt = 5 if o4 else 4
+        targets, src = pairs[:nt], [int(x) for x in pairs[nt:nt + 13]]
+        plans = [(src[0:2], 0.0), (src[2:5], 0.0), (src[5:7], -eps * 15 / 16),
+                 (src[7:9], -eps * 17 / 16)] + ([(src[9:13], 0.0)] if o4 else [])
+        for m, (ss, off) in zip(targets, plans):
+            v = lam[2 * ss[0]]
+            for x in ss[1:]:
+                v = v + lam[2 * x]
+            v = v + off
+            lam[2 * m], lam[2 * m + 1] = v, np.conj(v)
+        if _min_gap(lam) >= 1e-3:
+            break
+    else:
+        raise ValueError(f"no clamp spectrum with distinct eigenvalues in {MAX_DRAWS} draws")
+    V = _eigvecs(n, rng)
+    A = {M: dense_tensor(n, M, float(n) ** (-M / 2.0), rng) for M in orders if M >= 2}
+    return _finish(name, n, lam, V, A, {M: None for M in A}, eps=eps, **kw)
 
 
 # ----------------------------------------------------------------------------- hash tensors

@@ -9,7 +9,7 @@ import csv
 
 import pytest
 
-from paper_2509_08968_amd import counters as C
+import bench_counters as C
 
 W = "batch256-o3-blocksparse"
 

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_2509_08968_amd import binding as B
 from paper_2509_08968_amd import inputs as I
-from tests.helpers import rel
+from tests.helpers import check
 
 pytestmark = pytest.mark.gpu
 
@@ -51,8 +51,8 @@ def check_against(results, ss, ref):
     for q, (s, (npf, Ps)) in enumerate(zip(ss, results)):
         modes, P, cols = ref[q]
         for M in s.orders:
-            assert rel(Ps[M][modes], P[M]) <= TOL, (q, s.n, M)
-        assert rel(npf[:, modes], cols) <= TOL, (q, s.n)
+            check(Ps[M][modes], P[M], TOL, f"system {q} n={s.n} P_{M}")
+        check(npf[:, modes].T, cols.T, TOL, f"system {q} n={s.n} NPF")
 
 
 @pytest.mark.parametrize("budget", [0, 6 << 30])
@@ -64,8 +64,8 @@ def test_batch_matches_oracle_and_single_runs(torch_dev, mixed_reference, budget
     for s, (npf, Ps) in zip(ss, res):
         one, P1 = B.compute(s, "bf16x3")
         for M in s.orders:
-            assert rel(Ps[M], P1[M]) <= 1e-12, (s.n, M)
-        assert rel(npf, one) <= 1e-12, s.n
+            check(Ps[M], P1[M], 1e-12, f"n={s.n} P_{M} vs single")
+        check(npf.T, one.T, 1e-12, f"n={s.n} NPF vs single")
 
 
 def test_batch_graph_replay_and_autotuner(torch_dev, mixed_reference):
@@ -115,6 +115,37 @@ def test_workload_batch256_sampled(torch_dev):
         P = {M: oracle.sym(s, M, modes=modes)["P"] for M in s.orders}
         npf, Ps = res[q]
         for M in s.orders:
-            assert rel(Ps[M][modes], P[M]) <= TOL, (q, s.n, M)
+            check(Ps[M][modes], P[M], TOL, f"system {q} n={s.n} P_{M}")
         z = np.stack([s.delta * s.U[i, :] for i in modes])
-        assert rel(npf[:, modes], s.V[:, modes] * (z + sum(P.values())).T) <= TOL, (q, s.n)
+        check(npf[:, modes].T, s.V[:, modes].T * (z + sum(P.values())), TOL, f"system {q} NPF")
+
+
+def test_batch_more_argument_sets_than_cached_graphs(torch_dev):
+    """Six argument sets (distinct output buffers) through one batch: the first four are
+    captured and replayed, the rest run eagerly, no cached graph is destroyed while the
+    batch lives, and every run equals the eager result bitwise.  The batch is then destroyed
+    right after enqueueing a replay (its graphs are released once that launch is done)."""
+    torch, dev = torch_dev
+    ss = [I.block_sparse_system(n, [2, 3], 7200 + n) for n in (24, 40, 70)]
+    print("[batch argument sets] 3 systems, 6 sets", flush=True)
+    devs = [B.upload_system(s, dev) for s in ss]
+    b = B.Batch(ss)
+    ws = b.workspace(dev)
+    mk = lambda: ([torch.empty((s.order_max - 1, s.n, s.n), dtype=torch.complex128, device=dev)
+                   for s in ss], [torch.empty((s.n, s.n), dtype=torch.complex128, device=dev) for s in ss])
+    Pe, Ne = mk()
+    b.run(devs, ws, Pe, Ne, torch.cuda.default_stream())        # NULL stream: eager
+    torch.cuda.synchronize()
+    st = torch.cuda.Stream()
+    sets = [mk() for _ in range(6)]
+    for rep in range(2):
+        for k, (Pg, Ng) in enumerate(sets):
+            b.run(devs, ws, Pg, Ng, st)
+            torch.cuda.synchronize()
+            for q in range(len(ss)):
+                assert torch.equal(Pg[q], Pe[q]) and torch.equal(Ng[q], Ne[q]), (rep, k, q)
+    b.run(devs, ws, sets[0][0], sets[0][1], st)                  # a replay still in flight
+    b.close()
+    torch.cuda.synchronize()
+    for q in range(len(ss)):
+        assert torch.equal(sets[0][0][q], Pe[q]) and torch.equal(sets[0][1][q], Ne[q]), q

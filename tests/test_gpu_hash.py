@@ -19,7 +19,7 @@ import pytest
 import oracle
 from paper_2509_08968_amd import binding as B
 from paper_2509_08968_amd import inputs as I
-from tests.helpers import rel
+from tests.helpers import check
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +61,7 @@ def test_hash_source_equals_stored_tensor(torch_dev, precision):
     assert np.array_equal(a, b)
     ref = {M: oracle.sym(s, M)["P"] for M in s.orders}
     for M in s.orders:
-        assert rel(Pa[M], ref[M]) <= TOL[precision], M
+        check(Pa[M], ref[M], TOL[precision], f"P_{M}")
 
 
 # name -> (builder, output modes per block or 0 for the planner's choice, precisions)
@@ -80,10 +80,10 @@ def _sampled(s, ref_modes, precision, block_modes, budget=0):
     ref = {M: oracle.sym(s, M, modes=ref_modes)["P"] for M in s.orders}
     npf, Ps = B.compute(s, precision, block_modes=block_modes, budget_bytes=budget)
     for M in s.orders:
-        assert rel(Ps[M][ref_modes], ref[M]) <= TOL[precision], f"P_{M}"
+        check(Ps[M][ref_modes], ref[M], TOL[precision], f"P_{M}")
     z = np.stack([s.delta * s.U[i, :] for i in ref_modes])
     npf_cols = s.V[:, ref_modes] * (z + sum(ref.values())).T
-    assert rel(npf[:, ref_modes], npf_cols) <= TOL[precision], "NPF"
+    check(npf[:, ref_modes].T, npf_cols.T, TOL[precision], "NPF")
 
 
 @pytest.mark.timeout(600)
@@ -97,16 +97,18 @@ def test_large_n_sampled_modes(torch_dev, case, precision):
 
 
 @pytest.mark.timeout(900)
-def test_workload_n200_o4_hash_sampled(torch_dev):
-    """n=200, orders 2-4, dense hash-generated tensors (never stored), 96 GiB workspace
-    budget (13 blocks of 16 output modes); P rows and NPF columns of the sampled modes
+@pytest.mark.parametrize("precision", ["bf16x3", "fp32", "fp64"])
+def test_workload_n200_o4_hash_sampled(torch_dev, precision):
+    """n=200, orders 2-4, dense hash-generated tensors (never stored), in the configuration
+    the benchmark times (its workspace budget); P rows and NPF columns of the sampled modes
     against the oracle values stored by tests/golden/make_hash200_golden.py."""
+    import bench
     g = json.load(open(GOLD200))
     s = I.workload_hash200()
     modes = g["modes"]
-    print(f"[n200-o4-hash bf16x3] modes {modes}", flush=True)
-    npf, Ps = B.compute(s, "bf16x3", budget_bytes=96 << 30)
+    print(f"[n200-o4-hash {precision}] modes {modes}", flush=True)
+    npf, Ps = B.compute(s, precision, budget_bytes=bench.budget_for("n200-o4-dense-hash", precision))
     cplx = lambda a: np.asarray(a)[..., 0] + 1j * np.asarray(a)[..., 1]
     for M in s.orders:
-        assert rel(Ps[M][modes], cplx(g["P"][str(M)])) <= TOL["bf16x3"], f"P_{M}"
-    assert rel(npf[:, modes], cplx(g["npf_columns"]).T) <= TOL["bf16x3"], "NPF"
+        check(Ps[M][modes], cplx(g["P"][str(M)]), TOL[precision], f"P_{M}")
+    check(npf[:, modes].T, cplx(g["npf_columns"]), TOL[precision], "NPF")

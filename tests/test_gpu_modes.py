@@ -1,0 +1,159 @@
+"""Output-mode selection, conjugate pairs and the Taylor input convention on the GPU,
+through the C ABI.
+
+- A real system's conjugate modes (paper Section III keeps the modes that matter; a real
+  A_M makes mode conj(j)'s C, h, P row and NPF column the conjugates of mode j's): a plan
+  that computes one mode of each pair and fills the other equals the full plan to 1e-12
+  (FP64; the Psi rows of a pair are conjugate only to rounding), is bitwise deterministic
+  and matches the oracle in every precision, at n <= 64 and n > 64, with several blocks.
+- A subset of output modes (the critical modes): their P rows and NPF columns match the
+  oracle, and nothing else of the outputs is written.
+- Taylor-coefficient input (eq. (1) as printed): the same NPFs as the derivative input.
+- The staged entry points on a selecting plan: C rows of the computed modes, P rows of the
+  computed and filled modes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_08968_amd import binding as B
+from paper_2509_08968_amd import inputs as I
+from tests.helpers import check
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.lib()
+    return torch, "cuda:0"
+
+
+CASES = {
+    "n24-o3-blocksparse": lambda: I.block_sparse_system(24, [2, 3], 9301),
+    "n37-o3-dense-odd": lambda: I.dense_system(37, [2, 3], 9302),       # one real mode
+    "n64-o3-blocksparse": I.workload_sparse64,
+    "n100-o4-dense": lambda: I.dense_system(100, [2, 3, 4], 9303),
+    "n20-o3-resonant": lambda: I.resonant_system(20, [2, 3], 3105, n_res2=1, n_res3=1),
+}
+
+
+def _ref(s, modes=None):
+    modes = list(range(s.n)) if modes is None else list(modes)
+    P = {M: oracle.sym(s, M, modes=modes)["P"] for M in s.orders}
+    z = np.stack([s.delta * s.U[i, :] for i in modes])
+    return modes, P, s.V[:, modes].T * (z + sum(P.values()))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_conjugate_pairs_match_full_and_oracle(torch_dev, case, precision):
+    s = CASES[case]()
+    print(f"[conj {precision}] {case}", flush=True)
+    sel = None if s.n <= 64 else sorted({0, 1, 2, 3, s.n // 2, s.n // 2 + 1, s.n - 2, s.n - 1})
+    modes, P, cols = _ref(s, sel)
+    npf_c, Pc = B.compute(s, precision, conj=True)
+    npf_c2, Pc2 = B.compute(s, precision, conj=True)
+    for M in s.orders:
+        assert np.array_equal(Pc[M], Pc2[M]), "not deterministic"
+        check(Pc[M][modes], P[M], TOL[precision], f"P_{M}")
+    check(npf_c[:, modes].T, cols, TOL[precision], "NPF")
+    assert np.array_equal(npf_c, npf_c2)
+    if precision == "fp64":
+        npf_f, Pf = B.compute(s, "fp64")
+        for M in s.orders:
+            check(Pc[M], Pf[M], 1e-12, f"P_{M} conj vs full")
+        check(npf_c.T, npf_f.T, 1e-12, "NPF conj vs full")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("n", [40, 72])
+def test_conjugate_pairs_several_blocks(torch_dev, precision, n):
+    """Blocks of 16 computed modes against one block: bitwise at n <= 64; above, the
+    partial-sum slots of the t-range kernels depend on the block's width, so the FP64 sums
+    of the same per-item partials are grouped differently (agreement to rounding)."""
+    s = I.dense_system(n, [2, 3], 9304)
+    print(f"[conj blocks {precision}] n={n} J=16", flush=True)
+    one, P1 = B.compute(s, precision, conj=True)
+    many, Pm = B.compute(s, precision, conj=True, block_modes=16)
+    for M in s.orders:
+        if n <= 64:
+            assert np.array_equal(P1[M], Pm[M]), M
+        else:
+            check(Pm[M], P1[M], 1e-13, f"P_{M} blocks vs one")
+    if n <= 64:
+        assert np.array_equal(one, many)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("conj", [False, True])
+def test_output_mode_subset(torch_dev, precision, conj):
+    """Critical modes only: their rows and columns match the oracle, the rest of P_out and
+    npf_out is not written (it keeps the NaN it was filled with)."""
+    s = I.dense_system(90, [2, 3], 9305)
+    modes = [3, 40, 41, 7, 88, 2]
+    print(f"[subset {precision} conj={conj}] n=90 modes {modes}", flush=True)
+    npf, Ps = B.compute(s, precision, modes=modes, conj=conj)
+    srt = sorted(modes)
+    _, P, cols = _ref(s, srt)
+    for M in s.orders:
+        check(Ps[M][srt], P[M], TOL[precision], f"P_{M}")
+        rest = np.setdiff1d(np.arange(s.n), srt)
+        assert np.isnan(Ps[M][rest]).all(), "rows outside the subset were written"
+    check(npf[:, srt].T, cols, TOL[precision], "NPF")
+    assert np.isnan(npf[:, np.setdiff1d(np.arange(s.n), srt)]).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_taylor_convention(torch_dev, precision):
+    """A_M given as Taylor coefficients A_M / M! with NPF_A_TAYLOR gives the NPFs of the
+    derivative tensors A_M (the oracle's convention)."""
+    import dataclasses
+    s = I.dense_system(30, [2, 3, 4], 9306)
+    print(f"[taylor {precision}] n=30 orders 2-4", flush=True)
+    t = dataclasses.replace(s, A={M: a / math.factorial(M) for M, a in s.A.items()})
+    modes, P, cols = _ref(s)
+    npf, Ps = B.compute(t, precision, taylor=True)
+    for M in s.orders:
+        check(Ps[M], P[M], TOL[precision], f"P_{M}")
+    check(npf.T, cols, TOL[precision], "NPF")
+
+
+def test_staged_steps_on_selecting_plan(torch_dev):
+    """npf_modal_contract / npf_normal_form / npf_assemble with output modes and pairs:
+    C and h rows of the computed modes against the oracle, P rows of the computed and the
+    filled modes."""
+    torch, dev = torch_dev
+    s = I.dense_system(26, [2, 3], 9307)
+    conj = B.conj_pairs(s.lam)
+    modes = [0, 1, 5, 10, 11, 20]
+    print(f"[staged selecting] n=26 modes {modes}", flush=True)
+    d = B.upload_system(s, dev)
+    plan = B.Plan(s.n, s.order_max, "fp64", s.eps, s.tau, s.delta, modes=modes, conj_of=conj)
+    comp, filled = plan.modes()
+    assert comp == [0, 5, 10, 20] and filled == [1, -1, 11, -1]
+    ws = plan.workspace(dev)
+    for M in s.orders:
+        ref = oracle.sym(s, M, modes=comp, want_C=True, want_h=True)
+        C = torch.empty((len(comp), plan.unique_tuples[M]), dtype=torch.complex128, device=dev)
+        plan.modal_contract(M, B.NPF_ALL_BLOCKS, d.tensors[M - 2], d.U, d.V, ws, C)
+        torch.cuda.synchronize()
+        check(C.cpu().numpy(), ref["C"], TOL["fp64"], f"C_{M}")
+        plan.normal_form(M, B.NPF_ALL_BLOCKS, d.lam, C)
+        torch.cuda.synchronize()
+        check(C.cpu().numpy(), ref["h"], TOL["fp64"], f"h_{M}")
+        P = torch.zeros((s.n, s.n), dtype=torch.complex128, device=dev)
+        plan.assemble(M, B.NPF_ALL_BLOCKS, C, d.U, P)
+        torch.cuda.synchronize()
+        Pn = P.cpu().numpy()
+        want = oracle.sym(s, M, modes=sorted(modes))["P"]
+        check(Pn[sorted(modes)], want, TOL["fp64"], f"P_{M}")
+        rest = np.setdiff1d(np.arange(s.n), modes)
+        assert not Pn[rest].any()
+    plan.close()

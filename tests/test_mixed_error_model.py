@@ -1,13 +1,13 @@
-"""The error model behind the mixed-precision bound for plans beyond four orders (CPU only).
+"""The error model behind the mixed paths' order limit (CPU only).
 
 Emulates the arithmetic of the mixed paths in numpy: the chain of contractions in complex64
 with every intermediate rounded, C read at the sorted representative of each index tuple
 (so one rounding serves all of a tuple's orderings, as under symmetric packing), then the
-divisor, quotient and reduction of Alg. 2 steps 5-19 in FP64.  The GPU test's bound is 2.5
-times the largest emulated relative P error on this system (1.04e-6, order 5); the emulated
-errors must stay within half of that bound, and the same
-arithmetic without the shared rounding (each ordering rounded on its own) must be clearly
-smaller -- which is what separates rounding replicated by the packing from a defect.
+divisor, quotient and reduction of Alg. 2 steps 5-19 in FP64.  Through order 4 the emulated
+relative P error stays well inside the mixed paths' 1e-6 bound; at order 5 the shared
+rounding (up to 120 orderings per tuple) takes it to the bound itself, which is why plans
+in FP32 or split-BF16 stop at order 4.  The same arithmetic with each ordering rounded on
+its own is clearly smaller -- rounding replicated by the packing, not a defect.
 """
 import itertools
 import math
@@ -18,8 +18,8 @@ import oracle
 from paper_2509_08968_amd import inputs as I
 from tests.helpers import HIGH_ORDER_CASES, rel
 
-BOUND = 2.6e-6          # the GPU test's bound for mixed paths beyond four orders
-MARGIN = 2.0
+BOUND = 1e-6            # the mixed paths' bound on the relative error of P
+MARGIN = 1.5
 
 
 def _full(s, M):
@@ -46,7 +46,7 @@ def _P_from_C(s, M, C):
     return -(h @ Z)
 
 
-def test_shared_rounding_explains_the_high_order_bound():
+def test_shared_rounding_limits_mixed_paths_to_order_four():
     s = HIGH_ORDER_CASES["n18-o5-dense"]()
     n = s.n
     for M in s.orders:
@@ -60,6 +60,9 @@ def test_shared_rounding_explains_the_high_order_bound():
         ref = oracle.sym(s, M)["P"]
         e_shared = rel(_P_from_C(s, M, C_shared), ref)
         e_own = rel(_P_from_C(s, M, C), ref)
-        assert e_shared <= BOUND / MARGIN, (M, e_shared)
+        if M <= 4:
+            assert e_shared <= BOUND / MARGIN, (M, e_shared)
+        else:
+            assert e_shared > BOUND / MARGIN, (M, e_shared)
         assert e_own < e_shared, (M, e_own, e_shared)
         assert e_own <= 5e-7, (M, e_own)

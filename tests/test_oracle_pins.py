@@ -373,3 +373,23 @@ def test_invalid_arguments_rejected():
     s.eps = 1e-9
     with pytest.raises(ValueError):
         oracle.sym(s, 2, modes=[3])
+
+
+@pytest.mark.parametrize("n,orders", [(28, [2, 3]), (40, [2, 3, 4])])
+def test_clamp_systems_reach_the_clamp(n, orders):
+    """The clamp systems' planted divisors are exact: the oracle's h equals C / eps at the
+    exact resonances of every order and at |D| = (15/16) eps, and equals C / D (not C / eps)
+    at |D| = (17/16) eps."""
+    s = I.clamp_system(n, orders, 9100 + n)
+    for M in orders:
+        out = oracle.sym(s, M, want_C=True, want_h=True)
+        tups = I.sorted_tuples(n, M)
+        D = s.lam[tups].sum(1)[None, :] - s.lam[:, None]
+        clamp = np.abs(D) < s.eps
+        assert clamp.sum() >= 2, M
+        assert np.array_equal(out["h"][clamp], out["C"][clamp] / s.eps)
+        if M == 2:
+            assert np.any((D != 0) & clamp)                      # the one just below
+            above = (np.abs(D) > s.eps) & (np.abs(D) < 1.1 * s.eps)
+            assert above.sum() >= 2
+            assert np.array_equal(out["h"][above], out["C"][above] / D[above])

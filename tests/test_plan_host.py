@@ -5,6 +5,7 @@ import json
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2509_08968_amd import binding as B
@@ -96,3 +97,73 @@ def test_plan_accepts_the_largest_size():
     assert p.unique_tuples[4] == 259 * 258 * 257 * 256 // 24
     assert p.block_modes * p.n_blocks >= 256
     p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_mixed_plans_refuse_orders_above_four(precision):
+    """The FP32 and split-BF16 paths meet their 1e-6 bound up to order 4 only: plans of
+    five or six orders in those precisions are refused, FP64 plans accepted."""
+    for N in (5, 6):
+        with pytest.raises(B.NpfError) as e:
+            B.Plan(12, N, precision)
+        assert e.value.code == B.NPF_E_UNSUPPORTED
+        B.Plan(12, N, "fp64").close()
+    B.Plan(12, 4, precision).close()
+
+
+def test_output_modes_and_conjugate_pairs():
+    """Output modes {1, 4, 5} of six modes paired (0,1), (2,3), (4,5): mode 1 is computed
+    (its partner is not requested), 4 is computed and fills 5."""
+    conj = [1, 0, 3, 2, 5, 4]
+    p = B.Plan(6, 3, "fp64", modes=[4, 1, 5], conj_of=conj)
+    assert p.output_modes == 3 and p.computed_modes == 2
+    assert p.modes() == ([1, 4], [-1, 5])
+    p.close()
+    lam = np.empty(64, complex)
+    lam[0::2], lam[1::2] = np.arange(32) + 2j, np.arange(32) - 2j
+    q = B.Plan(64, 3, "bf16x3", conj_of=B.conj_pairs(lam))
+    assert q.computed_modes == 32 and q.output_modes == 64
+    assert q.modes()[1] == list(range(1, 64, 2))
+    full = B.Plan(64, 3, "bf16x3")
+    assert full.computed_modes == 64 and full.modes()[1] == [-1] * 64
+    assert q.workspace_bytes < full.workspace_bytes
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(modes=[1, 1]), "twice"), (dict(modes=[6]), "outside"), (dict(modes=[-1]), "outside"),
+    (dict(conj_of=[1, 0, 3, 2, 5, 5]), "involution"), (dict(conj_of=[1, 2, 0, 3, 4, 5]), "involution"),
+])
+def test_output_mode_lists_are_validated(kw, msg):
+    with pytest.raises(B.NpfError) as e:
+        B.Plan(6, 2, "fp64", **kw)
+    assert e.value.code == B.NPF_E_INVALID and msg in str(e.value)
+
+
+def test_host_copies_check_preconditions():
+    """Psi Phi = I and the conjugate pairing are checked when host copies are given."""
+    from paper_2509_08968_amd import inputs as I
+    s = I.dense_system(10, [2], 55)
+    conj = B.conj_pairs(s.lam)
+    B.Plan(10, 2, "fp64", conj_of=conj, check=(s.U, s.V, s.lam)).close()
+    with pytest.raises(B.NpfError, match="identity"):
+        B.Plan(10, 2, "fp64", check=(s.U.T.copy(), s.V, None))
+    bad = s.lam.copy()
+    bad[1] += 1e-3
+    with pytest.raises(B.NpfError, match="eigenvalues"):
+        B.Plan(10, 2, "fp64", conj_of=conj, check=(None, None, bad))
+    V2 = s.V.copy()
+    V2[:, 1] *= 1j                           # still an eigenvector, no longer the conjugate
+    U2 = np.linalg.inv(V2)
+    with pytest.raises(B.NpfError, match="right eigenvectors"):
+        B.Plan(10, 2, "fp64", conj_of=conj, check=(U2, V2, s.lam))
+    with pytest.raises(B.NpfError, match="convention"):
+        prob = B.NpfProblem(10, 2, 0, 1e-9, 1e-2, 1.0, 0, 0, 0, 0, 7)
+        h = ctypes.c_void_p()
+        B._check(B.lib().npf_plan_create(ctypes.byref(prob), ctypes.byref(h)), "npf_plan_create")
+
+
+def test_conj_pairs_of_a_spectrum():
+    lam = np.array([1 + 2j, 3 + 0j, 1 - 2j, -1 - 1j, -1 + 1j])
+    assert B.conj_pairs(lam).tolist() == [2, 1, 0, 4, 3]
+    with pytest.raises(ValueError):
+        B.conj_pairs(np.array([1 + 2j, 1 + 1j]))
