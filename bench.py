@@ -5,11 +5,14 @@ One step = one pass of the whole hot path over the workload: plan (Alg. 1 block 
 upper-index contraction, the lower-index chain, divisor / division, reduction to P_M
 for every order, and the NPF assembly (Alg. 2), with inputs already resident in HBM.
 
-Prints ONE JSON line: modal tensor entries per second (sum over orders of n * U_M
-symmetric-unique entries per step / step time) for the selected precision, the same for
-the plain FP64 GPU path, the error of both against the CPU FP64 oracle, the roofline of
-the dominant kernel (timed live with HIP events on its launch stream) and the oracle's
-own rate on the host cores.
+Default workload: n = 200 states, orders 2-4, dense derivative tensors generated on the
+device (never stored).  Prints ONE JSON line: modal tensor entries per second (sum over
+orders of n * U_M symmetric-unique entries of the full NPF per step / step time) for the
+selected precision (split-BF16), the same for the FP32 and plain FP64 GPU paths, the error
+of each against the CPU FP64 oracle (pooled, per output mode and max-entry), the roofline of
+the dominant kernel (timed live with HIP events on its launch stream) and the oracle's own
+rate on the host cores.  A real system's modes come in conjugate pairs: by default one
+mode of each pair is computed and the other filled by conjugation (--no-conj computes all).
 """
 import argparse
 import json
@@ -23,7 +26,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "modal tensor entries/s + MFMA util, split-BF16 vs FP64 GPU at ≤1e-6 rel err"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}   # dense MFMA, MI355X
+# Dense matrix-core peaks of MI355X for the engine each path runs on: FP64, FP64 (the FP32
+# path forms exact FP32 products and accumulates in FP64 on the FP64 matrix cores), BF16.
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 78.6, "bf16x3": 2500.0}
 PEAK_VALU_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}
 HBM_GBPS = 8000.0
 DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16"}
@@ -133,18 +138,21 @@ def sysm_support(sysm):
     return getattr(sysm, "support_max", 0) or 8
 
 
-def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0, progress=False):
-    """Time `steps` steps on a dedicated stream (graph replay after the first call), then,
-    if `profile`, run the same steps eagerly with HIP events around every kernel launch.
-    With `progress` (multi-second steps) every step is synchronised and logged."""
+def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0, progress=False,
+              conj=True):
+    """Time `steps` steps on a dedicated stream (graph replay after the first call), then
+    run `profile` more steps eagerly with HIP events around every kernel launch.  With
+    `progress` (multi-second steps) every step is synchronised and logged.  With `conj` the
+    plan computes one mode of each conjugate pair and fills the other (a real system)."""
     import torch
     from paper_2509_08968_amd import binding as B
 
     n, N = s.n, s.order_max
     P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
     npf = torch.empty((n, n), dtype=torch.complex128, device=device)
+    conj_of = B.conj_pairs(s.lam) if conj else None
     mk = lambda: B.Plan(n, N, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
-                        support_max=s.support_max)
+                        support_max=s.support_max, conj_of=conj_of)
     plan0 = mk()
     ws = plan0.workspace(device)
     stream = torch.cuda.Stream(device=device)       # default priority
@@ -182,7 +190,7 @@ def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0, prog
         plans = []
         e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e2.record(stream)
-        for i in range(steps):
+        for i in range(profile):
             p = mk()
             p.profile(True)            # eager launches, an event pair around each kernel
             step(p)
@@ -192,7 +200,8 @@ def time_path(sysm, s, precision, steps, warmup, device, profile, budget=0, prog
                 log(f"[bench] {precision} profiled step {i + 1}/{steps} done")
         e3.record(stream)
         torch.cuda.synchronize()
-        out["eager_ms_per_step"] = e2.elapsed_time(e3) / steps
+        out["eager_ms_per_step"] = e2.elapsed_time(e3) / profile
+        out["profile_steps"] = profile
         for p in plans:
             for k, (cnt, tot) in p.kernel_times().items():
                 c0, t_ = out["kernels"].get(k, (0, 0.0))
@@ -207,37 +216,81 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def cpu_baseline(s, entries, target_s=10.0):
-    """The oracle as it stands, timed on this host's cores over a bounded sample: the full
-    workload repeated until about target_s seconds have passed (small systems), or one
-    output mode of every order (large systems), scaled to modal entries per second."""
-    import oracle
+def err_summary(got, ref):
+    """Errors of a result whose rows are output modes: pooled relative Frobenius error,
+    the largest per-mode relative error (each row against its own norm) and the max-entry
+    error max|got - ref| / max|ref|."""
+    import numpy as np
+    got, ref = np.atleast_2d(got), np.atleast_2d(ref)
+    d = np.linalg.norm(got - ref, axis=1)
+    nb = np.linalg.norm(ref, axis=1)
+    per = d / np.where(nb > 0, nb, 1.0)
+    return {"pooled": rel(got, ref), "per_mode_max": float(per.max()),
+            "max_entry": float(np.abs(got - ref).max() / np.abs(ref).max())}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads the oracle may use on this host: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when it is set (the machine's CPU share)."""
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        cores = min(cores, int(env))
+    return max(1, cores)
+
+
+def cpu_baseline(s, entries, target_s=10.0):
+    """The oracle as it stands, timed on this host's cores over a bounded sample, scaled to
+    modal entries per second: all the threads this host gives the process, and one thread.
+    Small systems: the full workload repeated until about target_s seconds have passed.
+    Large systems (the oracle takes minutes per mode at order 4): output mode 0 of every
+    order with all threads, mode 0 of the orders below 4 with one thread."""
+    import oracle
+    cores = host_threads()
+
+    def run(threads, orders, modes):
+        t0, reps, done = time.perf_counter(), 0, 0
+        while True:
+            for M in orders:
+                oracle.sym(s, M, modes=modes, nthreads=threads)
+                done += (s.n if modes is None else len(modes)) * math.comb(s.n + M - 1, M)
+            reps += 1
+            el = time.perf_counter() - t0
+            if modes is not None or el >= target_s or reps >= 1000:
+                return done, el, reps
+
     if s.n > 64:
-        t0 = time.perf_counter()
-        for M in s.orders:
-            oracle.sym(s, M, modes=[0], nthreads=cores)
-        el = time.perf_counter() - t0
-        done = sum(math.comb(s.n + M - 1, M) for M in s.orders)
+        done, el, _ = run(cores, s.orders, [0])
+        low = [M for M in s.orders if M < 4]
+        d1, e1, _ = run(1, low, [0])
         return {"value": done / el, "unit": "modal entries/s", "cores": cores, "kind": "oracle",
-                "sample": f"one output mode (mode 0) of orders {s.orders}: {done} entries in "
-                          f"{el:.1f} s, packed-symmetric FP64 oracle with {cores} OpenMP threads"}
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        for M in s.orders:
-            oracle.sym(s, M, nthreads=cores)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or reps >= 1000:
-            break
-    return {"value": entries * reps / el, "unit": "modal entries/s", "cores": cores,
-            "kind": "oracle",
+                "cpu_model": cpu_model(),
+                "sample": f"output mode 0 of orders {s.orders}: {done} entries in {el:.1f} s, "
+                          f"packed-symmetric FP64 oracle with {cores} OpenMP threads",
+                "one_thread": {"value": d1 / e1, "cores": 1,
+                               "sample": f"output mode 0 of orders {low}: {d1} entries in "
+                                         f"{e1:.1f} s, one thread"}}
+    done, el, reps = run(cores, s.orders, None)
+    d1, e1, r1 = run(1, s.orders, None)
+    return {"value": done / el, "unit": "modal entries/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"full workload (all output modes, orders {s.orders}) x {reps} repeats, "
-                      f"{el:.1f} s, packed-symmetric FP64 oracle with {cores} OpenMP threads"}
+                      f"{el:.1f} s, packed-symmetric FP64 oracle with {cores} OpenMP threads",
+            "one_thread": {"value": d1 / e1, "cores": 1,
+                           "sample": f"the same x {r1} repeats, {e1:.1f} s, one thread"}}
 
 
 BATCH_WORKLOAD = "batch256-o3-blocksparse"
@@ -307,7 +360,10 @@ def bench_batch(args):
         for M in s.orders:
             ref = oracle.sym(s, M, modes=modes)["P"]
             got = P[q][M - 2].cpu().numpy()[modes]
-            errs[f"P{M}"] = max(errs.get(f"P{M}", 0.0), rel(got, ref))
+            e = err_summary(got, ref)
+            cur = errs.setdefault(f"P{M}", {k: 0.0 for k in e})
+            for k, v in e.items():
+                cur[k] = max(cur[k], v)
 
     roof = None
     if not args.no_profile:
@@ -358,7 +414,7 @@ def bench_batch(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+        cores = host_threads()
         small = [ss[int(i)] for i in order[:24]]
         t0 = time.perf_counter()
         done = 0
@@ -368,6 +424,7 @@ def bench_batch(args):
                 done += s.n * math.comb(s.n + M - 1, M)
         el = time.perf_counter() - t0
         cpu = {"value": done / el, "unit": "modal entries/s", "cores": cores, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"the 24 smallest systems of the batch in full (orders 2-3, all modes): "
                          f"{done} entries in {el:.1f} s, packed-symmetric FP64 oracle with "
                          f"{cores} OpenMP threads"}
@@ -392,22 +449,44 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+DEFAULT_WORKLOAD = "n200-o4-dense-hash"
+
+
+def leg_counts(args, s, which):
+    """Timed and warmup steps of a comparison leg: as given, else the main leg's for steps
+    of milliseconds and one timed step without warmup for the multi-second n > 128 steps."""
+    st = getattr(args, f"{which}_steps")
+    wu = getattr(args, f"{which}_warmup")
+    big = s.n > 128
+    return (st if st is not None else (1 if big else args.steps),
+            wu if wu is not None else (0 if big else args.warmup))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="n64-o3-blocksparse")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-conj", action="store_true",
+                    help="compute every mode (default: one of each conjugate pair, the other "
+                         "filled by conjugation)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=2,
+                    help="eager steps with an event pair around every kernel (0: none)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
-    ap.add_argument("--fp64-steps", type=int, default=None,
-                    help="timed steps of the FP64 comparison (default: --steps)")
-    ap.add_argument("--fp64-warmup", type=int, default=None,
-                    help="warmup steps of the FP64 comparison (default: --warmup)")
+    for leg in ("fp64", "fp32"):
+        ap.add_argument(f"--{leg}-steps", type=int, default=None,
+                        help=f"timed steps of the {leg.upper()} comparison (default: --steps, "
+                             "or 1 for systems above 128 states)")
+        ap.add_argument(f"--{leg}-warmup", type=int, default=None,
+                        help=f"warmup steps of the {leg.upper()} comparison (default: --warmup, "
+                             "or 0 for systems above 128 states)")
     ap.add_argument("--no-tune", action="store_true", help="batch workload: skip the autotuner")
     ap.add_argument("--no-solo", action="store_true", help="batch workload: skip per-system runs")
     args = ap.parse_args()
@@ -435,7 +514,8 @@ def main():
     copy_probe(args, device)
     s = I.WORKLOADS[args.workload]()
     sysm = B.upload_system(s, device)
-    log(f"[bench] workload {args.workload}: n={s.n} orders={s.orders}")
+    conj = not args.no_conj
+    log(f"[bench] workload {args.workload}: n={s.n} orders={s.orders} conjugate pairs={conj}")
 
     # Oracle reference (outside every timed region): P rows and NPF columns of the modes.
     t0 = time.perf_counter()
@@ -453,35 +533,39 @@ def main():
     log(f"[bench] oracle reference ({len(modes)} modes) in {time.perf_counter() - t0:.1f} s")
 
     def errors(r):
-        e = {f"P{M}": rel(r["P"][M][modes], refP[M]) for M in s.orders}
-        e["npf"] = rel(r["npf"][:, modes], ref_npf)
+        e = {f"P{M}": err_summary(r["P"][M][modes], refP[M]) for M in s.orders}
+        e["npf"] = err_summary(r["npf"][:, modes].T, ref_npf.T)
         return e
 
     progress = s.n > 128
-    res = time_path(sysm, s, args.precision, args.steps, args.warmup, device,
-                    not args.no_profile, budget_for(args.workload, args.precision), progress)
+    profile = 0 if args.no_profile else args.profile_steps
+    res = time_path(sysm, s, args.precision, args.steps, args.warmup, device, profile,
+                    budget_for(args.workload, args.precision), progress, conj)
     plan = res["plan"]
     entries = plan.modal_entries
     value = entries / (res["ms_per_step"] * 1e-3)
     err = errors(res)
     log(f"[bench] {args.precision}: {res['ms_per_step']:.3f} ms/step, {value:.3e} entries/s, err {err}")
 
-    fp64 = None
-    if args.precision != "fp64" and not args.no_fp64:
+    def leg(prec):
         torch.cuda.empty_cache()
-        st64 = args.steps if args.fp64_steps is None else args.fp64_steps
-        wu64 = args.warmup if args.fp64_warmup is None else args.fp64_warmup
-        r64 = time_path(sysm, s, "fp64", st64, wu64, device, False,
-                        budget_for(args.workload, "fp64"), progress)
-        v64 = entries / (r64["ms_per_step"] * 1e-3)
-        e64 = errors(r64)
-        fp64 = {"value": v64, "ms_per_step": r64["ms_per_step"], "rel_err": e64,
-                "speedup_of_selected": v64 and value / v64, "steps": st64, "warmup": wu64,
-                "budget_bytes": budget_for(args.workload, "fp64")}
-        log(f"[bench] fp64: {r64['ms_per_step']:.3f} ms/step, {v64:.3e} entries/s, err {e64}")
+        st, wu = leg_counts(args, s, prec)
+        r = time_path(sysm, s, prec, st, wu, device, 0, budget_for(args.workload, prec),
+                      progress, conj)
+        v = entries / (r["ms_per_step"] * 1e-3)
+        e = errors(r)
+        log(f"[bench] {prec}: {r['ms_per_step']:.3f} ms/step, {v:.3e} entries/s, err {e}")
+        return {"value": v, "ms_per_step": r["ms_per_step"], "rel_err": e,
+                "speedup_of_selected": value / v, "steps": st, "warmup": wu,
+                "budget_bytes": budget_for(args.workload, prec),
+                "block_modes": r["plan"].block_modes, "blocks": r["plan"].n_blocks}
+
+    legs = {p: leg(p) for p in ("fp32", "fp64")
+            if p != args.precision and not getattr(args, f"no_{p}")}
 
     roof = None
     if res["kernels"]:
+        psteps = res["profile_steps"]
         name, (cnt, tot) = max(res["kernels"].items(), key=lambda kv: kv[1][1])
         flops, byts, bound, mfma = kernel_work(name, sysm, plan)
         avg_s = tot / cnt * 1e-3
@@ -494,13 +578,14 @@ def main():
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak,
                 "traffic": measured_traffic(args.workload, args.precision, name),
-                "algorithmic_bytes": byts, "kernel": name,
-                "avg_launch_ms": tot / cnt, "launches_per_step": cnt / args.steps,
-                "share_of_step": tot / args.steps / res["ms_per_step"],
-                "timing": "HIP events around every launch, eager pass of the same steps"}
+                "algorithmic_bytes": byts, "algorithmic_flops": flops, "kernel": name,
+                "avg_launch_ms": tot / cnt, "launches_per_step": cnt / psteps,
+                "share_of_step": tot / psteps / res["ms_per_step"],
+                "timing": f"HIP events around every launch on its stream, {psteps} eager "
+                          "steps after the timed ones"}
         if mfma:
             roof["executed_mfma_frac"] = achieved * SPLIT_PRODUCTS[args.precision] / peak
-        log(f"[bench] kernels: " + ", ".join(f"{k}={v[1] / args.steps:.3f}ms"
+        log(f"[bench] kernels: " + ", ".join(f"{k}={v[1] / psteps:.3f}ms"
                                              for k, v in sorted(res['kernels'].items())))
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(s, entries)
@@ -512,11 +597,16 @@ def main():
         "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": args.workload, "n": s.n, "orders": s.orders,
                    "precision": args.precision, "modal_entries_per_step": entries,
+                   "conjugate_pairs": conj, "output_modes": plan.output_modes,
+                   "computed_modes": plan.computed_modes,
                    "block_modes": plan.block_modes, "blocks": plan.n_blocks,
-                   "workspace_bytes": plan.workspace_bytes, "oracle_checked_modes": modes},
+                   "workspace_bytes": plan.workspace_bytes,
+                   "budget_bytes": budget_for(args.workload, args.precision),
+                   "oracle_checked_modes": modes},
         "eager_ms_per_step": res.get("eager_ms_per_step"),
         "rel_err_vs_oracle": err,
-        "fp64_gpu": fp64,
+        "fp64_gpu": legs.get("fp64"),
+        "fp32_gpu": legs.get("fp32"),
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -5,6 +5,11 @@
 //   f64 16x16x4 : A[i=c][k=g], B[k=g][j=c], D reg r holds D[4r + g][c]
 //   f32 16x16x4 : A[i=c][k=g], B[k=g][j=c], D reg r holds D[4g + r][c]
 //   bf16 16x16x32: A[i=c][k=8g+s], B[k=8g+s][j=c] (s = 0..7), D reg r holds D[4g + r][c]
+//
+// The FP32 engine keeps its operands and stored intermediates in FP32 but forms the products
+// exactly and accumulates them in FP64, on the FP64 matrix cores: with FP32 accumulation
+// (one rounding per four products) a chain of contractions over 200 states lost up to
+// 1.1e-6 relative in P, the whole margin of the mixed paths' bound.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,7 +34,7 @@ template <> struct EngT<Eng::F64> {
     static constexpr int TC = 16;   // t per chunk of the fused kernel
 };
 template <> struct EngT<Eng::F32> {
-    using acc = v4f;
+    using acc = v4d;                // FP64 accumulation of exact FP32 x FP32 products
     using real = float;
     using cplx = float2;
     static constexpr int KS = 4;
@@ -46,7 +51,7 @@ template <> struct EngT<Eng::BF3> {
 // Row of the 16x16 output tile held in accumulator register r by lane group g.
 template <Eng E> __device__ __forceinline__ int out_row(int r, int g)
 {
-    if constexpr (E == Eng::F64) return 4 * r + g;
+    if constexpr (E == Eng::F64 || E == Eng::F32) return 4 * r + g;
     else return 4 * g + r;
 }
 
@@ -54,9 +59,10 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ v4f mfma(float a, float b, v4f c)
+// FP32 operands into an FP64 accumulator: the product of two FP32 values is exact in FP64.
+__device__ __forceinline__ v4d mfma(float a, float b, v4d c)
 {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(double(a), double(b), c, 0, 0, 0);
 }
 __device__ __forceinline__ v4f mfma(v8bf a, v8bf b, v4f c)
 {

@@ -144,7 +144,7 @@ stage_mfma(StageArgs a)
                 const int64_t t = int64_t(tt) * 16 + out_row<E>(r, g);
                 if (t < m || t >= a.n) continue;
                 const int64_t row = rp + colex_term_c(t, a.i);
-                dst[row * a.U_suf * a.Jpad] = cplx{sr[tt][r], si[tt][r]};
+                dst[row * a.U_suf * a.Jpad] = cplx{real(sr[tt][r]), real(si[tt][r])};
             }
         }
     }

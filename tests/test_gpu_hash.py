@@ -107,7 +107,8 @@ def test_workload_n200_o4_hash_sampled(torch_dev, precision):
     s = I.workload_hash200()
     modes = g["modes"]
     print(f"[n200-o4-hash {precision}] modes {modes}", flush=True)
-    npf, Ps = B.compute(s, precision, budget_bytes=bench.budget_for("n200-o4-dense-hash", precision))
+    npf, Ps = B.compute(s, precision, conj=True,
+                        budget_bytes=bench.budget_for("n200-o4-dense-hash", precision))
     cplx = lambda a: np.asarray(a)[..., 0] + 1j * np.asarray(a)[..., 1]
     for M in s.orders:
         check(Ps[M][modes], cplx(g["P"][str(M)]), TOL[precision], f"P_{M}")

@@ -89,13 +89,15 @@ def test_run_is_deterministic(torch_dev):
         assert np.array_equal(Pa[M], Pb[M])
 
 
+@pytest.mark.parametrize("conj", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
-def test_workload_n64_o3_blocksparse_full(torch_dev, precision):
-    """The benchmarked workload at full size (n=64, orders 2-3, block-sparse)."""
+def test_workload_n64_o3_blocksparse_full(torch_dev, precision, conj):
+    """The n=64, orders 2-3, block-sparse workload at full size, every mode computed or one
+    of each conjugate pair."""
     s = I.workload_sparse64()
-    print(f"[n64-o3-blocksparse {precision}]", flush=True)
+    print(f"[n64-o3-blocksparse {precision} conj={conj}]", flush=True)
     ref, npf_ref = _oracle_all(s)
-    npf, Ps = B.compute(s, precision)
+    npf, Ps = B.compute(s, precision, conj=conj)
     for M in s.orders:
         check(Ps[M], ref[M]["P"], TOL[precision], f"P_{M}")
     check(npf.T, npf_ref.T, TOL[precision], "NPF")
@@ -225,13 +227,15 @@ def dense128():
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("precision", ["bf16x3", "fp32", "fp64"])
 def test_workload_n128_o4_dense_sampled(torch_dev, dense128, precision):
-    """n=128, orders 2-4, dense, under a 64 GiB workspace budget (two output-mode blocks).
-    P_M rows and NPF columns of the sampled modes are compared with the oracle: each mode's
-    chain is independent, so these are exact checks of the full-size run."""
+    """n=128, orders 2-4, dense, under a 64 GiB workspace budget, one mode of each
+    conjugate pair computed (the benchmark's configuration).  P_M rows and NPF columns of
+    the sampled modes are compared with the oracle, each mode on its own: each mode's chain
+    is independent, so these are exact checks of the full-size run (mode 5 is filled by
+    conjugation from mode 4)."""
     torch, dev = torch_dev
     s, modes, ref = dense128
     print(f"[n128-o4 {precision}] modes {modes}", flush=True)
-    npf, Ps = B.compute(s, precision, budget_bytes=64 << 30)
+    npf, Ps = B.compute(s, precision, budget_bytes=64 << 30, conj=True)
     for M in s.orders:
         check(Ps[M][modes], ref[M], TOL[precision], f"P_{M}")
     z = np.stack([s.delta * s.U[i, :] for i in modes])          # [modes, states]
