@@ -159,6 +159,7 @@ extern "C" int npf_modal_contract(npf_plan_t plan, int32_t order, int64_t block,
     for (int64_t b = b0; b < b1 && rc == NPF_OK; ++b) {
         int64_t j0, J;
         block_modes(plan, b, j0, J);
+        const BlockShape shape(plan, J);
         rc = run_chain(plan, order, j0, J, A, U, V, ws, s, tucker);
         if (rc) break;
         double *dst = static_cast<double *>(C_out) + 2 * (j0 - b0 * plan->J) * plan->U[order];
@@ -397,6 +398,7 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
         for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
             int64_t j0, J;
             block_modes(plan, b, j0, J);
+            const BlockShape shape(plan, J);
             rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, sm, tucker);
             if (rc) break;
             {

@@ -96,17 +96,17 @@ prepare(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double
     }
 }
 
-// h' = S W / D for one element; FP64 divisor, FP64 or FP32 division.
-template <Eng E>
-__device__ __forceinline__ void scaled_quotient(typename EngT<E>::real sr, typename EngT<E>::real si,
-                                                double2 d, double w, double tau2,
+// h' = S W / D for one element; FP64 divisor, FP64 or FP32 division (the FP32 engine, whose
+// products are accumulated in FP64, divides in FP64 too: one rounding of h' to FP32).
+template <Eng E, typename Sv>
+__device__ __forceinline__ void scaled_quotient(Sv sr, Sv si, double2 d, double w, double tau2,
                                                 typename EngT<E>::real &hr, typename EngT<E>::real &hi)
 {
     const double den = d.x * d.x + d.y * d.y;
-    if constexpr (E == Eng::F64) {
+    if constexpr (E == Eng::F64 || E == Eng::F32) {
         const double f = w / den;
-        hr = (sr * d.x + si * d.y) * f;
-        hi = (si * d.x - sr * d.y) * f;
+        hr = (double(sr) * d.x + double(si) * d.y) * f;
+        hi = (double(si) * d.x - double(sr) * d.y) * f;
     } else {
         if (den < tau2) {
             const double f = w / den;

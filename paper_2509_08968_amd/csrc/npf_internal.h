@@ -137,6 +137,21 @@ struct OrderLayout {
 }  // namespace npf
 
 namespace npf {
+// While alive, launches for a block of J modes use the block's own width: a last block
+// narrower than the others runs with Jpad = J rounded up to 16 (the layout fits any).
+struct BlockShape {
+    npf_plan_s *plan;
+    int64_t saved;
+    BlockShape(npf_plan_s *p, int64_t J) : plan(p), saved(p->Jpad)
+    {
+        const int64_t w = (J + 15) / 16 * 16;
+        if (w < p->Jpad) p->Jpad = w;
+    }
+    ~BlockShape() { plan->Jpad = saved; }
+};
+}  // namespace npf
+
+namespace npf {
 // Brackets one kernel launch with an event pair when the plan is profiling.
 struct Timed {
     npf_plan_s *plan;

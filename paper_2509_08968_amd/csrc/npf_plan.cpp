@@ -31,7 +31,17 @@ int64_t binom(int64_t a, int64_t b)
 
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-// Workspace layout for a block of Jpad output modes.
+// Partial-P slots x block width of the widest layout any block of at most Jpad modes uses
+// (a narrower last block may write more slots of fewer modes).
+static int64_t parts_elems(const npf_plan_s &p, int64_t Jpad)
+{
+    int64_t e = 0;
+    for (int64_t w = 16; w <= Jpad; w += 16)
+        e = std::max(e, std::max<int64_t>(1, fused_max_slots(&p, w)) * w);
+    return e;
+}
+
+// Workspace layout for blocks of at most Jpad output modes.
 static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
 {
     Layout L;
@@ -57,8 +67,7 @@ static Layout make_layout(const npf_plan_s &p, int64_t Jpad)
     L.phi_bytes = p.npad * p.npad * 16 * 4;
     L.phi = take(L.phi_bytes);
     if (p.select) L.msel = take(p.nc * (p.n + 1) * 16);
-    const int64_t nparts = std::max<int64_t>(1, fused_max_slots(&p, Jpad));
-    L.parts_bytes = nparts * Jpad * p.n * 16;
+    L.parts_bytes = parts_elems(p, Jpad) * p.n * 16;
     L.parts = take(L.parts_bytes);
     const int smax = p.prob.support_max;
     if (smax >= 1 && smax <= kTuckerMaxSupport && p.N >= 2) {
@@ -93,7 +102,6 @@ static Layout make_split_layout(const npf_plan_s &p, int64_t Jpad, Layout *ord)
     C.phi_bytes = p.npad * p.npad * 16 * 4;
     C.phi = take(C.phi_bytes);
     if (p.select) C.msel = take(p.nc * (p.n + 1) * 16);
-    const int64_t nparts = std::max<int64_t>(1, fused_max_slots(&p, Jpad));
     const int smax = p.prob.support_max;
     for (int M = 2; M <= p.N; ++M) {
         Layout L = C;
@@ -104,7 +112,7 @@ static Layout make_split_layout(const npf_plan_s &p, int64_t Jpad, Layout *ord)
         L.buf[0] = take(per[0]);
         L.buf[1] = take(per[1]);
         L.pm = take(p.n * p.n * 16);
-        L.parts_bytes = nparts * Jpad * p.n * 16;
+        L.parts_bytes = parts_elems(p, Jpad) * p.n * 16;
         L.parts = take(L.parts_bytes);
         if (tucker_route(&p, M)) {
             L.tk.over = take(p.n * 4);
@@ -313,8 +321,13 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
             return fail(NPF_E_BUDGET, "memory budget below the smallest block (16 modes)");
         }
     }
+    // Balanced blocks, or full blocks of Jpad modes and a narrower last one when that pads
+    // fewer modes (100 modes under a 32-mode limit: 32 + 32 + 32 + 16 rather than 4 x 32).
     p->n_blocks = (nc + Jpad - 1) / Jpad;
-    p->J = (nc + p->n_blocks - 1) / p->n_blocks;
+    const int64_t J_bal = (nc + p->n_blocks - 1) / p->n_blocks;
+    const int64_t padded_bal = p->n_blocks * round_up(J_bal, 16);
+    const int64_t padded_full = (p->n_blocks - 1) * Jpad + round_up(nc - (p->n_blocks - 1) * Jpad, 16);
+    p->J = padded_full < padded_bal ? Jpad : J_bal;
     p->Jpad = round_up(p->J, 16);
     p->lay = make_layout(*p, p->Jpad);
     for (int M = 0; M <= NPF_MAX_ORDER; ++M) p->ord[M] = p->lay;

@@ -157,3 +157,29 @@ def test_staged_steps_on_selecting_plan(torch_dev):
         rest = np.setdiff1d(np.arange(s.n), modes)
         assert not Pn[rest].any()
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_narrow_last_block(torch_dev, precision):
+    """Blocks of at most 32 computed modes over 100 modes run as 32 + 32 + 32 + 16 (the last
+    block narrower, fewer padded modes than four balanced blocks of 32): against one block of
+    all modes (agreement to rounding: the t-range kernels group the same per-item partials
+    by block width; in split-BF16 the upper-index contraction of a block of at most 32
+    modes takes the BF16 matrix cores, that of one block of 100 the FP64 ones, so the two
+    agree to the mixed bound) and the oracle on sampled modes, including the narrow
+    block's."""
+    s = I.dense_system(100, [2, 3], 9308)
+    plan = B.Plan(s.n, s.order_max, precision, block_modes=32)
+    assert plan.n_blocks == 4 and plan.block_modes == 32
+    plan.close()
+    print(f"[narrow last block {precision}] n=100 J=32", flush=True)
+    one, P1 = B.compute(s, precision)
+    many, Pm = B.compute(s, precision, block_modes=32)
+    for M in s.orders:
+        check(Pm[M], P1[M], 1e-13 if precision != "bf16x3" else 2 * TOL[precision],
+              f"P_{M} blocks vs one")
+    modes = [0, 31, 32, 95, 96, 99]
+    _, P, cols = _ref(s, modes)
+    for M in s.orders:
+        check(Pm[M][modes], P[M], TOL[precision], f"P_{M}")
+    check(many[:, modes].T, cols, TOL[precision], "NPF")
