@@ -1,7 +1,8 @@
 // Straightforward (SIMT) kernels of the hot path: the upper-index contraction, one stage
 // of the lower-index chain, the last stage into C, the divisor / division, the reduction
 // to P and the NPF assembly.  These serve the step-by-step entry points and are the
-// reference structure for the fused MFMA kernels.
+// reference structure for the fused MFMA kernels.  The mixed paths store their results in
+// FP32 but these kernels sum in FP64 (a sequential FP32 sum over 150 states lost 3e-7).
 #include "npf_device.h"
 #include "npf_internal.h"
 
@@ -269,7 +270,7 @@ hipError_t launch_psi_a(const ChainArgs &a)
                                p.Jpad, reinterpret_cast<double2 *>(dst), hashed, a.A->seed,
                                a.A->scale, a.M);
         else
-            hipLaunchKernelGGL((psi_a_dense<float2, float>), dim3(grid_for(UM * p.Jpad)),
+            hipLaunchKernelGGL((psi_a_dense<float2, double>), dim3(grid_for(UM * p.Jpad)),
                                dim3(kThreads), 0, a.stream, a.A->values, Psi, p.n, UM, a.j0, a.J,
                                p.Jpad, reinterpret_cast<float2 *>(dst), hashed, a.A->seed,
                                a.A->scale, a.M);
@@ -287,7 +288,7 @@ hipError_t launch_psi_a(const ChainArgs &a)
             hipLaunchKernelGGL((fill_zero<float2>), dim3(grid_for(UM * p.Jpad)), dim3(kThreads),
                                0, a.stream, reinterpret_cast<float2 *>(dst), UM * p.Jpad);
             if (total > 0)
-                hipLaunchKernelGGL((psi_a_sparse<float2, float>), dim3(grid_for(total)),
+                hipLaunchKernelGGL((psi_a_sparse<float2, double>), dim3(grid_for(total)),
                                    dim3(kThreads), 0, a.stream, a.A->values, a.A->col_rank,
                                    a.A->col_ptr, a.A->row_k, a.A->ncols, Psi, p.n, a.j0, a.J,
                                    p.Jpad, reinterpret_cast<float2 *>(dst));
@@ -322,7 +323,7 @@ hipError_t launch_stage(const ChainArgs &a, int i)
                            reinterpret_cast<double2 *>(dst), Phi, p.n, M, i, U_prev, U_suf, U_in,
                            a.J, p.Jpad, p.U[M], 1.0, items);
     else
-        hipLaunchKernelGGL((stage_simt<float2, float2, float, false>), dim3(grid), dim3(kThreads),
+        hipLaunchKernelGGL((stage_simt<float2, float2, double, false>), dim3(grid), dim3(kThreads),
                            shm, a.stream, reinterpret_cast<const float2 *>(src),
                            reinterpret_cast<float2 *>(dst), Phi, p.n, M, i, U_prev, U_suf, U_in,
                            a.J, p.Jpad, p.U[M], 1.0, items);
@@ -348,7 +349,7 @@ hipError_t launch_last_to_c(const ChainArgs &a, double *C_out)
                            reinterpret_cast<double2 *>(C_out), Phi, p.n, M, i, U_prev, U_suf,
                            U_in, a.J, p.Jpad, p.U[M], p.a_scale[M] / fact, items);
     else
-        hipLaunchKernelGGL((stage_simt<float2, double2, float, true>), dim3(grid), dim3(kThreads),
+        hipLaunchKernelGGL((stage_simt<float2, double2, double, true>), dim3(grid), dim3(kThreads),
                            shm, a.stream, reinterpret_cast<const float2 *>(src),
                            reinterpret_cast<double2 *>(C_out), Phi, p.n, M, i, U_prev, U_suf,
                            U_in, a.J, p.Jpad, p.U[M], p.a_scale[M] / fact, items);
