@@ -191,7 +191,7 @@ static int check_host_copies(const npf_problem &q)
                     return fail(NPF_E_INVALID, "Psi Phi differs from the identity by more than check_tol");
             }
     if (!q.conj_of) return NPF_OK;
-    auto maxabs = [n](const cd *x, int64_t count) {
+    auto maxabs = [](const cd *x, int64_t count) {
         double m = 0.0;
         for (int64_t e = 0; e < count; ++e) m = std::max(m, std::abs(x[e]));
         return m > 0.0 ? m : 1.0;
