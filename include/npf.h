@@ -298,6 +298,20 @@ int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
             const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
             void *stream);
 
+/* npf_run for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same launch sequence, run eagerly with
+ * the orders in sequence, on a workspace the library holds itself -- a static device array of
+ * NPF_STATIC_WORKSPACE_BYTES per GPU, held until the process ends.  Allocates nothing.
+ * Returns NPF_E_UNSUPPORTED when the plan's workspace_bytes exceed that size (plan with
+ * NPF_FLAG_SERIAL_ORDERS or fewer modes per block to shrink it), NPF_E_INVALID for the
+ * argument errors of npf_run or a plan that is profiling.  Every call on a GPU uses that
+ * GPU's one array: calls that overlap on one GPU (on different streams or host threads)
+ * race and must be serialised by the caller.  No part of the workspace needs clearing: each
+ * call writes every part it reads before reading it. */
+#define NPF_STATIC_WORKSPACE_BYTES (256ll << 20)
+int npf_run_static(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
+                   const void *lambda, void *P_out, void *npf_out, void *stream);
+
 /* Alg. 1 (batched derivative tensor) arithmetic, host only: for a tensor with n_dim
  * dimensions of extent n_s, bytes_per_entry bytes per entry and a limit of m_limit_gb
  * GiB per batch, writes the batch count per dimension BC[n_dim], the largest batch

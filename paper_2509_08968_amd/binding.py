@@ -28,7 +28,7 @@ EXPORTED = [
     "npf_plan_profile", "npf_plan_kernel_times", "npf_error_string", "npf_last_error",
     "npf_hash_fill", "npf_batch_create", "npf_batch_info", "npf_batch_destroy",
     "npf_batch_run", "npf_batch_tune", "npf_batch_launches", "npf_batch_time",
-    "npf_plan_modes",
+    "npf_plan_modes", "npf_run_static",
 ]
 A_DERIVATIVE, A_TAYLOR = 0, 1
 
@@ -114,6 +114,7 @@ def lib():
         L.npf_assemble.argtypes = [P, i32, i64, P, P, P, P]
         L.npf_finalize.argtypes = [P, P, P, P, P, P]
         L.npf_run.argtypes = [P, ctypes.POINTER(NpfTensor), P, P, P, P, i64, P, P, P]
+        L.npf_run_static.argtypes = [P, ctypes.POINTER(NpfTensor), P, P, P, P, P, P]
         L.npf_alg1_batches.argtypes = [i32, i64, dbl, i32, ctypes.POINTER(i64),
                                        ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                        ctypes.POINTER(dbl)]
@@ -140,7 +141,7 @@ def lib():
                   "npf_assemble", "npf_finalize", "npf_run", "npf_plan_profile",
                   "npf_plan_kernel_times", "npf_hash_fill", "npf_batch_create",
                   "npf_batch_info", "npf_batch_run", "npf_batch_tune", "npf_batch_launches",
-                  "npf_batch_time", "npf_plan_modes"):
+                  "npf_batch_time", "npf_plan_modes", "npf_run_static"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -288,6 +289,13 @@ class Plan:
     def finalize(self, U, V, P_sum, npf_out, stream=None):
         _check(lib().npf_finalize(self._h, _ptr(U), _ptr(V), _ptr(P_sum), _ptr(npf_out),
                                   _stream(stream)), "npf_finalize")
+
+    def run_static(self, tensors: List["DeviceTensor"], U, V, lam, P_out=None, npf_out=None,
+                   stream=None):
+        """npf_run_static: the hot path on the library's own static workspace."""
+        arr = (NpfTensor * len(tensors))(*[t.desc for t in tensors])
+        _check(lib().npf_run_static(self._h, arr, _ptr(U), _ptr(V), _ptr(lam), _ptr(P_out),
+                                    _ptr(npf_out), _stream(stream)), "npf_run_static")
 
     def run(self, tensors: List["DeviceTensor"], U, V, lam, ws, P_out=None, npf_out=None,
             stream=None):

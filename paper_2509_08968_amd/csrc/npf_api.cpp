@@ -299,6 +299,21 @@ const SideSet *side_set()
 
 }  // namespace
 
+namespace npf {
+int run_eager_checked(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
+                      const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
+                      hipStream_t s)
+{
+    if (!plan) return fail(NPF_E_INVALID, "null plan");
+    if (!A || !U || !V || !lambda || !ws) return fail(NPF_E_INVALID, "null argument");
+    if (ws_bytes < plan->lay.total) return fail(NPF_E_INVALID, "workspace smaller than planned");
+    int rc = NPF_OK;
+    for (int M = 2; M <= plan->N; ++M)
+        if ((rc = check_tensor(plan, &A[M - 2], M))) return rc;
+    return run_eager(plan, A, U, V, lambda, ws, P_out, npf_out, s);
+}
+}  // namespace npf
+
 extern "C" int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
                        const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
                        void *stream)

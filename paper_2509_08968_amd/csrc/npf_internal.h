@@ -273,6 +273,11 @@ hipError_t launch_psi_a_mfma(const ChainArgs &a);
 // MFMA version of one chain stage (n <= 256).
 bool stage_mfma_supported(const npf_plan_s *p);
 hipError_t launch_stage_mfma(const ChainArgs &a, int i);
+// The launch sequence of npf_run, eagerly (no graph, orders in sequence), on workspace ws
+// of ws_bytes bytes, after npf_run's argument checks.
+int run_eager_checked(npf_plan_s *plan, const npf_tensor *A, const void *U, const void *V,
+                      const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
+                      hipStream_t s);
 // Fill `count` doubles with zero.
 hipError_t launch_zero(double *x, int64_t count, hipStream_t s);
 // dst[i] += src[i] (or dst = src when first), count doubles.
