@@ -11,7 +11,9 @@ Functions follow the paper (arXiv 2509.08968):
               stored, or generated entry by entry for hash-generated tensors);
   hash_values()  entries of a hash-generated tensor, from the C generator;
   assemble()  Alg. 2 step 20 / eq. (7): NPF[k, i] = Phi[k, i] (delta Psi[i, k] + sum_M P_M[i, k]);
-  npf()       orders 2..N of one system, summed and assembled.
+  npf()       orders 2..N of one system, summed and assembled;
+  interaction()  eqs. (8)-(9): pNM[k, i] = Phi[k, i] sum_t h_M[i, t] prod_l zeta*_k[t_l] with the
+              corrected zeta*_k = delta Psi[:, k] + sum_M P_M[:, k] (z(0) of eq. (7)).
 """
 from __future__ import annotations
 
@@ -58,9 +60,12 @@ def lib():
             L.npfo_hash_value.argtypes = [ctypes.c_uint64, dbl, i32, i64, i64]
             L.npfo_hash_value.restype = dbl
             L.npfo_assemble.argtypes = [i64, P, P, dbl, P, P]
+            L.npfo_sym_z.argtypes = [i64, i32, P, P, P, P, dbl, P, P, i64, P, i32]
+            L.npfo_full_z.argtypes = [i64, i32, P, P, P, P, dbl, P, P]
             L.npfo_binom.argtypes = [i64, i64]
             L.npfo_binom.restype = i64
-            for f in (L.npfo_full, L.npfo_sym, L.npfo_sym_hash, L.npfo_assemble):
+            for f in (L.npfo_full, L.npfo_sym, L.npfo_sym_hash, L.npfo_assemble, L.npfo_sym_z,
+                      L.npfo_full_z):
                 f.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -192,3 +197,49 @@ def npf(sys, method: str = "sym", nthreads: int = 0):
         Ps[M] = full(sys, M)["P"] if method == "full" else sym(sys, M, nthreads=nthreads)["P"]
     Psum = sum(Ps.values()) if Ps else None
     return assemble(sys, Psum), Ps
+
+
+def reduce_with(sys, M: int, Z, modes=None, method: str = "sym", nthreads: int = 0):
+    """The reduction of Alg. 2 steps 12-19 with the factor matrix Z[a, k] in place of
+    zeta = delta Psi: P[q, k] = -sum_t h_M[modes[q], t] prod_l Z[t_l, k] (packed tensors,
+    or the full-tensor tier for small n)."""
+    n = sys.n
+    Zc = _c128(Z)
+    lam, V, U = _c128(sys.lam), _c128(sys.V), _c128(sys.U)
+    if method == "full":
+        A_full = np.ascontiguousarray(unpack_full(sys.A[M], n, M), dtype=np.float64)
+        P = np.empty((n, n), np.complex128)
+        rc = lib().npfo_full_z(n, M, _p(lam), _p(V), _p(U), _p(A_full), sys.eps, _p(Zc), _p(P))
+        if rc != 0:
+            raise ValueError("npfo_full_z rejected its arguments")
+        return P if modes is None else P[np.asarray(modes)]
+    modes = np.arange(n, dtype=np.int64) if modes is None else np.asarray(modes, np.int64)
+    A = np.ascontiguousarray(sys.A[M], dtype=np.float64)
+    P = np.empty((len(modes), n), np.complex128)
+    rc = lib().npfo_sym_z(n, M, _p(lam), _p(V), _p(U), _p(A), sys.eps, _p(Zc), _p(modes),
+                          len(modes), _p(P), int(nthreads))
+    if rc != 0:
+        raise ValueError("npfo_sym_z rejected its arguments")
+    return P
+
+
+def zeta_star(sys, Ps):
+    """Eq. (9): zeta*[a, k] = delta Psi[a, k] + sum_M P_M[a, k] -- the nonlinear modal initial
+    condition z(0) of eq. (7) for the kick of state k (all modes a)."""
+    return sys.delta * _c128(sys.U) + sum(Ps.values())
+
+
+def interaction(sys, Ps=None, modes=None, method: str = "sym", nthreads: int = 0):
+    """Eq. (8): the interaction participation factors of every order M = 2..N, as
+    {M: [n states, len(modes)]} with pNM[k, i] = Phi[k, i] sum_t h_M[i, t] prod_l zeta*_k[t_l]
+    (modes: output modes, default all).  Ps: the P_M of every mode (computed if None)."""
+    if Ps is None:
+        Ps = {M: (full(sys, M)["P"] if method == "full" else sym(sys, M, nthreads=nthreads)["P"])
+              for M in sys.orders}
+    Z = zeta_star(sys, Ps)
+    cols = np.arange(sys.n) if modes is None else np.asarray(modes)
+    out = {}
+    for M in sys.orders:
+        Q = reduce_with(sys, M, Z, modes=cols, method=method, nthreads=nthreads)
+        out[M] = _c128(sys.V)[:, cols] * (-Q).T
+    return out

@@ -7,6 +7,9 @@
  *   eq. (7)      z(0) = zeta - h2 zeta zeta - .. - hN zeta..zeta, zeta = delta Psi[:, k]
  *   Alg. 2       steps 1-4 contraction, 5-9 divisor and clamp, 11 division,
  *                12-19 Khatri-Rao power of Psi and reduction, 20 assembly.
+ *   eqs. (8)-(9) interaction factors pNM[k,i] = Phi[k,i] sum_t h_M[i,t] prod_l zeta*_k[t_l],
+ *                with zeta*_k = delta Psi[:,k] + sum_M P_M[:,k] (= z(0) of eq. (7)): the same
+ *                reduction with zeta* in place of zeta (npfo_sym_z, npfo_full_z: P of zeta*).
  * Readings where the paper is silent (all listed in the design notes):
  *   - A_M is the derivative tensor, so the Taylor coefficient is A_M / M! (Alg. 2 step 4).
  *   - The divisor is summed over the sorted tuple left to right, then lam_j subtracted,
@@ -115,9 +118,35 @@ static void sort_small(int32_t *s, int m)
 }
 
 /* ------------------------------------------------------------------ full tensors */
+static int full_impl(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                     const double *A_full, double eps, double delta, const npfo_c *Z,
+                     npfo_c *C_full, npfo_c *h_full, npfo_c *P);
+
 int npfo_full(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
               const double *A_full, double eps, double delta,
               npfo_c *C_full, npfo_c *h_full, npfo_c *P)
+{
+    return full_impl(n, M, lam, Phi, Psi, A_full, eps, delta, NULL, C_full, h_full, P);
+}
+
+int npfo_full_z(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                const double *A_full, double eps, const npfo_c *Z, npfo_c *P)
+{
+    if (!Z) return -1;
+    return full_impl(n, M, lam, Phi, Psi, A_full, eps, 1.0, Z, NULL, NULL, P);
+}
+
+/* The reduction's factor for mode t and kicked state k: delta Psi[t, k] (eq. (7)), or the
+ * given Z[t, k] (the corrected zeta* of eq. (9) for the interaction factors of eq. (8)). */
+static npfo_c zeta_at(const npfo_c *Z, const npfo_c *Psi, double delta, int64_t n, int64_t t,
+                      int64_t k)
+{
+    return Z ? Z[t * n + k] : delta * Psi[t * n + k];
+}
+
+static int full_impl(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                     const double *A_full, double eps, double delta, const npfo_c *Z,
+                     npfo_c *C_full, npfo_c *h_full, npfo_c *P)
 {
     if (n < 1 || M < 2 || M > 8 || !lam || !Phi || !Psi || !A_full || !(eps > 0.0)) return -1;
     int64_t nm = 1;
@@ -173,8 +202,8 @@ int npfo_full(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo
                 for (int64_t t = 0; t < nm; ++t) {
                     int64_t rem = t;
                     for (int i = M - 1; i >= 0; --i) { digits[i] = (int32_t)(rem % n); rem /= n; }
-                    npfo_c z = delta * Psi[digits[0] * n + k];
-                    for (int i = 1; i < M; ++i) z = z * (delta * Psi[digits[i] * n + k]);
+                    npfo_c z = zeta_at(Z, Psi, delta, n, digits[0], k);
+                    for (int i = 1; i < M; ++i) z = z * zeta_at(Z, Psi, delta, n, digits[i], k);
                     s = s + h[j * nm + t] * z;
                 }
                 P[j * n + k] = -s;
@@ -225,8 +254,8 @@ double npfo_hash_value(uint64_t seed, double scale, int M, int64_t k, int64_t r)
 
 static int sym_impl(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
                     const double *A_packed, int hashed, uint64_t seed, double scale,
-                    double eps, double delta, const int64_t *modes, int64_t n_modes,
-                    npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads);
+                    double eps, double delta, const npfo_c *Z, const int64_t *modes,
+                    int64_t n_modes, npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads);
 
 int npfo_sym(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
              const double *A_packed, double eps, double delta,
@@ -234,8 +263,8 @@ int npfo_sym(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_
              npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads)
 {
     if (!A_packed) return -1;
-    return sym_impl(n, M, lam, Phi, Psi, A_packed, 0, 0, 0.0, eps, delta, modes, n_modes, C_sym,
-                    h_sym, P_rows, nthreads);
+    return sym_impl(n, M, lam, Phi, Psi, A_packed, 0, 0, 0.0, eps, delta, NULL, modes, n_modes,
+                    C_sym, h_sym, P_rows, nthreads);
 }
 
 int npfo_sym_hash(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
@@ -244,14 +273,23 @@ int npfo_sym_hash(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const 
                   npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads)
 {
     if (n > 512) return -1;
-    return sym_impl(n, M, lam, Phi, Psi, NULL, 1, seed, scale, eps, delta, modes, n_modes, C_sym,
-                    h_sym, P_rows, nthreads);
+    return sym_impl(n, M, lam, Phi, Psi, NULL, 1, seed, scale, eps, delta, NULL, modes, n_modes,
+                    C_sym, h_sym, P_rows, nthreads);
+}
+
+int npfo_sym_z(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+               const double *A_packed, double eps, const npfo_c *Z, const int64_t *modes,
+               int64_t n_modes, npfo_c *P_rows, int nthreads)
+{
+    if (!A_packed || !Z) return -1;
+    return sym_impl(n, M, lam, Phi, Psi, A_packed, 0, 0, 0.0, eps, 1.0, Z, modes, n_modes, NULL,
+                    NULL, P_rows, nthreads);
 }
 
 static int sym_impl(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
                     const double *A_packed, int hashed, uint64_t seed, double scale,
-                    double eps, double delta, const int64_t *modes, int64_t n_modes,
-                    npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads)
+                    double eps, double delta, const npfo_c *Z, const int64_t *modes,
+                    int64_t n_modes, npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads)
 {
     if (n < 1 || M < 2 || M > 8 || !lam || !Phi || !Psi || (!A_packed && !hashed) || !modes ||
         n_modes < 0 || !(eps > 0.0))
@@ -355,8 +393,8 @@ static int sym_impl(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, cons
                     npfo_c s = 0;
                     int64_t r = 0;
                     do {
-                        npfo_c z = delta * Psi[t[0] * n + k];
-                        for (int l = 1; l < M; ++l) z = z * (delta * Psi[t[l] * n + k]);
+                        npfo_c z = zeta_at(Z, Psi, delta, n, t[0], k);
+                        for (int l = 1; l < M; ++l) z = z * zeta_at(Z, Psi, delta, n, t[l], k);
                         s = s + multiplicity(t, M) * (h[r] * z);
                         ++r;
                     } while (next_sorted(t, M, n));

@@ -60,6 +60,18 @@ int npfo_sym(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_
              const int64_t *modes, int64_t n_modes,
              npfo_c *C_sym, npfo_c *h_sym, npfo_c *P_rows, int nthreads);
 
+/* The reduction of Alg. 2 steps 12-19 with a given factor matrix in place of zeta = delta Psi:
+ * P_rows[q*n + k] = - sum_{t in [n]^M} h[modes[q], t] prod_i Z[t_i*n + k] (sym: packed
+ * tensors, per selected mode) and P[j*n + k] likewise for every j (full: full tensors, small
+ * n).  With Z[a*n + k] = zeta*_k[a] (eq. (9): delta Psi[a,k] + sum_M P_M[a,k]), -P is the
+ * contraction of h_M with M factors zeta* whose Hadamard product with Phi gives the
+ * interaction participation factors of eq. (8). */
+int npfo_sym_z(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+               const double *A_packed, double eps, const npfo_c *Z, const int64_t *modes,
+               int64_t n_modes, npfo_c *P_rows, int nthreads);
+int npfo_full_z(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const npfo_c *Psi,
+                const double *A_full, double eps, const npfo_c *Z, npfo_c *P);
+
 /* Entry A_M[k, r] of a hash-generated tensor (seed, scale): SplitMix64 (Steele, Lea and
  * Flood 2014) output number (M << 49 | k << 40 | r) from the seed; S = sum of its four
  * 16-bit fields; value = ((S - 131070) * 2^-16 * sqrt(3)) * scale (Irwin-Hall sum of

@@ -30,16 +30,22 @@ MUTANTS = {
     "Psi transposed in G": ("                s = s + Psi[j * n + k] * a;",
                             "                s = s + Psi[k * n + j] * a;"),
     "multiplicity dropped": ("s = s + multiplicity(t, M) * (h[r] * z);", "s = s + (h[r] * z);"),
-    "delta dropped in zeta": ("npfo_c z = delta * Psi[t[0] * n + k];", "npfo_c z = Psi[t[0] * n + k];"),
-    "zeta index transposed": ("z = z * (delta * Psi[t[l] * n + k]);", "z = z * (delta * Psi[k * n + t[l]]);"),
+    "delta dropped in zeta": ("return Z ? Z[t * n + k] : delta * Psi[t * n + k];",
+                              "return Z ? Z[t * n + k] : Psi[t * n + k];"),
+    "zeta index transposed": ("return Z ? Z[t * n + k] : delta * Psi[t * n + k];",
+                              "return Z ? Z[t * n + k] : delta * Psi[k * n + t];"),
+    "zeta* index transposed": ("return Z ? Z[t * n + k] : delta * Psi[t * n + k];",
+                               "return Z ? Z[k * n + t] : delta * Psi[t * n + k];"),
+    "zeta* ignored": ("return Z ? Z[t * n + k] : delta * Psi[t * n + k];",
+                      "return delta * Psi[t * n + k];"),
     "assembly transposed": ("npfo_c z = delta * Psi[i * n + k];", "npfo_c z = delta * Psi[k * n + i];"),
     "assembly mode index": ("npf[k * n + i] = Phi[k * n + i] * z;", "npf[k * n + i] = Phi[i * n + k] * z;"),
     "clamp ignored": ("if (mag2 < eps * eps) d = eps;", "(void)mag2;"),
     "clamp sign": ("if (mag2 < eps * eps) d = eps;", "if (mag2 < eps * eps) d = -eps;"),
     "stage keeps unsorted tail": ("const int64_t last = (i > 1) ? p[i - 2] : 0;",
                                   "const int64_t last = 0;"),
-    "full sum skips a lower index": ("for (int i = 1; i < M; ++i) z = z * (delta * Psi[digits[i] * n + k]);",
-                                     "for (int i = 2; i < M; ++i) z = z * (delta * Psi[digits[i] * n + k]);"),
+    "full sum skips a lower index": ("for (int i = 1; i < M; ++i) z = z * zeta_at(Z, Psi, delta, n, digits[i], k);",
+                                     "for (int i = 2; i < M; ++i) z = z * zeta_at(Z, Psi, delta, n, digits[i], k);"),
 }
 
 PIN_CALLS = [
@@ -55,6 +61,8 @@ PIN_CALLS = [
     lambda: pins.test_p10_full_equals_sym(5, 3),
     lambda: pins.test_p10_full_equals_sym(4, 4),
     lambda: pins.test_clamp_exact_resonance(),
+    lambda: pins.test_p11_interaction_full_equals_sym(4, 2),
+    lambda: pins.test_p12_interaction_factors_reconstruct_the_kick([2], 3),
 ]
 
 

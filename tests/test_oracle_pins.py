@@ -393,3 +393,55 @@ def test_clamp_systems_reach_the_clamp(n, orders):
             above = (np.abs(D) > s.eps) & (np.abs(D) < 1.1 * s.eps)
             assert above.sum() >= 2
             assert np.array_equal(out["h"][above], out["C"][above] / D[above])
+
+
+# ------------------------------------------------------------------ eqs. (8)-(9): interaction
+@pytest.mark.parametrize("n,M", [(4, 2), (5, 3), (3, 4)])
+def test_p11_interaction_full_equals_sym(n, M):
+    """The reduction with a given factor matrix (zeta* of eq. (9)) on full tensors equals the
+    packed evaluation; with Z = delta Psi it is the ordinary P_M."""
+    s = small(n, M, 111 + 10 * n + M, delta=0.4)
+    rng = np.random.default_rng(n + M)
+    Z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    a = oracle.reduce_with(s, M, Z, method="full")
+    b = oracle.reduce_with(s, M, Z)
+    assert rel(b, a) < 1e-13
+    assert rel(oracle.reduce_with(s, M, s.delta * s.U), oracle.sym(s, M)["P"]) < 1e-14
+
+
+def _reconstruction_residual(s, k):
+    """Eq. (6) for the kick x(0) = delta e_k: sum over modes of the order-1 factor (eq. (7))
+    and the interaction factors (eq. (8)) reconstructs x_k(0) = delta."""
+    npf, Ps = oracle.npf(s)
+    inter = oracle.interaction(s, Ps)
+    return abs(npf[k].sum() + sum(p[k].sum() for p in inter.values()) - s.delta)
+
+
+@pytest.mark.parametrize("orders,slope", [([2], 3), ([3], 5), ([2, 3, 4], 3)])
+def test_p12_interaction_factors_reconstruct_the_kick(orders, slope):
+    """With z(0) = zeta* (eq. (9)) the normal-form map x = Phi (z + sum_M h_M(z, .., z)) of
+    eq. (3) returns the kicked state up to O(delta^(2M-1)) for a single order M (O(delta^3)
+    with order 2 present): the residual of eq. (6) must fall with that slope in delta.  A
+    dropped factor, a wrong sign of zeta* or of h gives slope M or 1."""
+    n, k = 5, 2
+    deltas = np.array([1e-3, 5e-4, 2.5e-4, 1.25e-4])     # the asymptotic range of this system
+    res = []
+    for d in deltas:
+        s = I.dense_system(n, orders, 1200 + sum(orders), delta=float(d))
+        res.append(_reconstruction_residual(s, k))
+    fit = np.polyfit(np.log(deltas), np.log(res), 1)[0]
+    assert abs(fit - slope) < 0.3, (fit, res)
+
+
+def test_p12_interaction_factor_scales_as_delta_power():
+    """pNM ~ delta^M, with the zeta* correction of relative size O(delta^(M-1)): halving
+    delta scales p3 by 1/8 up to a deviation that falls a hundredfold per tenfold smaller delta."""
+    dev = []
+    for d in (1e-4, 1e-5):
+        s = I.dense_system(5, [3], 1250, delta=d)
+        a = oracle.interaction(s)[3]
+        s.delta = d / 2
+        b = oracle.interaction(s)[3]
+        dev.append(rel(b, a * 0.5 ** 3))
+    assert dev[1] < 1e-7
+    assert 80 < dev[0] / dev[1] < 120, dev
