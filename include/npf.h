@@ -298,6 +298,22 @@ int npf_run(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
             const void *lambda, void *ws, int64_t ws_bytes, void *P_out, void *npf_out,
             void *stream);
 
+/* Interaction participation factors of eqs. (8)-(9), after the NPFs of npf_run (whose
+ * outputs P_out and npf_out it also writes, each nullable): with the corrected modal
+ * initial condition of eq. (9),
+ *   zeta*_k[a] = delta Psi[a,k] + sum_{M=2..N} P_M[a,k]      (= z(0) of eq. (7)),
+ * the factor of order M is
+ *   inpf_out[(M-2)*n*n + k*n + i] = Phi[k,i] sum_{t in [n]^M} h_M[i,t] prod_l zeta*_k[t_l]
+ * (pNM of state k in mode i, eq. (8): h_M contracted with M factors zeta*), for M = 2..N
+ * (inpf_out: [N-1][n][n] complex128, device).  The NPF of npf_run is the order-1 term of
+ * the decomposition of eq. (6).  Runs a second pass of every order's chain, last
+ * contraction and reduction with zeta* in place of zeta = delta Psi (about twice the time
+ * of npf_run).  Needs every mode's P row: NPF_E_UNSUPPORTED for a plan with output modes
+ * (conjugate pairs are fine).  Other errors as npf_run. */
+int npf_run_interaction(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V,
+                        const void *lambda, void *ws, int64_t ws_bytes, void *P_out,
+                        void *npf_out, void *inpf_out, void *stream);
+
 /* npf_run for callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): the same launch sequence, run eagerly with
  * the orders in sequence, on a workspace the library holds itself -- a static device array of

@@ -28,7 +28,7 @@ EXPORTED = [
     "npf_plan_profile", "npf_plan_kernel_times", "npf_error_string", "npf_last_error",
     "npf_hash_fill", "npf_batch_create", "npf_batch_info", "npf_batch_destroy",
     "npf_batch_run", "npf_batch_tune", "npf_batch_launches", "npf_batch_time",
-    "npf_plan_modes", "npf_run_static",
+    "npf_plan_modes", "npf_run_static", "npf_run_interaction",
 ]
 A_DERIVATIVE, A_TAYLOR = 0, 1
 
@@ -115,6 +115,8 @@ def lib():
         L.npf_finalize.argtypes = [P, P, P, P, P, P]
         L.npf_run.argtypes = [P, ctypes.POINTER(NpfTensor), P, P, P, P, i64, P, P, P]
         L.npf_run_static.argtypes = [P, ctypes.POINTER(NpfTensor), P, P, P, P, P, P]
+        L.npf_run_interaction.argtypes = [P, ctypes.POINTER(NpfTensor), P, P, P, P, i64, P, P, P,
+                                          P]
         L.npf_alg1_batches.argtypes = [i32, i64, dbl, i32, ctypes.POINTER(i64),
                                        ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                        ctypes.POINTER(dbl)]
@@ -141,7 +143,8 @@ def lib():
                   "npf_assemble", "npf_finalize", "npf_run", "npf_plan_profile",
                   "npf_plan_kernel_times", "npf_hash_fill", "npf_batch_create",
                   "npf_batch_info", "npf_batch_run", "npf_batch_tune", "npf_batch_launches",
-                  "npf_batch_time", "npf_plan_modes", "npf_run_static"):
+                  "npf_batch_time", "npf_plan_modes", "npf_run_static",
+                  "npf_run_interaction"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -290,6 +293,14 @@ class Plan:
         _check(lib().npf_finalize(self._h, _ptr(U), _ptr(V), _ptr(P_sum), _ptr(npf_out),
                                   _stream(stream)), "npf_finalize")
 
+    def run_interaction(self, tensors: List["DeviceTensor"], U, V, lam, ws, inpf_out, P_out=None,
+                        npf_out=None, stream=None):
+        """npf_run_interaction: the NPFs and the interaction factors of eqs. (8)-(9)."""
+        arr = (NpfTensor * len(tensors))(*[t.desc for t in tensors])
+        _check(lib().npf_run_interaction(self._h, arr, _ptr(U), _ptr(V), _ptr(lam), _ptr(ws),
+                                         ws.numel(), _ptr(P_out), _ptr(npf_out), _ptr(inpf_out),
+                                         _stream(stream)), "npf_run_interaction")
+
     def run_static(self, tensors: List["DeviceTensor"], U, V, lam, P_out=None, npf_out=None,
                    stream=None):
         """npf_run_static: the hot path on the library's own static workspace."""
@@ -405,13 +416,14 @@ def upload_system(sys, device, sparse: Optional[bool] = None,
 def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0,
             block_modes: int = 0, sparse: Optional[bool] = None, graph: bool = True,
             hash_source: bool = True, support_max: Optional[int] = None, modes=None,
-            conj: bool = False, taylor: bool = False, fill=None):
+            conj: bool = False, taylor: bool = False, fill=None, interaction: bool = False):
     """Run the fused hot path on one system; returns (NPF, {M: P_M}) as numpy arrays.
     support_max (default: the system's own bound, 0 when its tensors are not sent sparse)
     selects the lower-indices-first route for sparse orders.  modes: output modes (None =
     all); conj: compute one mode of each conjugate pair and fill the other; taylor: the
     system's A_M hold Taylor coefficients (NPF_A_TAYLOR).  Rows / columns that are not
-    written hold `fill` (default NaN)."""
+    written hold `fill` (default NaN).  interaction: also the interaction factors of
+    eqs. (8)-(9), returned third as {M: [n states, n modes]}."""
     import torch
     dev = upload_system(sys, device, sparse, hash_source)
     if support_max is None:
@@ -424,11 +436,17 @@ def compute(sys, precision: str = "fp64", device="cuda:0", budget_bytes: int = 0
     fv = complex(np.nan, np.nan) if fill is None else fill
     P = torch.full((N - 1, n, n), fv, dtype=torch.complex128, device=device)
     npf = torch.full((n, n), fv, dtype=torch.complex128, device=device)
-    plan.run(dev.tensors, dev.U, dev.V, dev.lam, ws, P, npf)
+    if interaction:
+        Q = torch.full((N - 1, n, n), fv, dtype=torch.complex128, device=device)
+        plan.run_interaction(dev.tensors, dev.U, dev.V, dev.lam, ws, Q, P, npf)
+    else:
+        plan.run(dev.tensors, dev.U, dev.V, dev.lam, ws, P, npf)
     torch.cuda.synchronize(device)
     Ps = {M: P[M - 2].cpu().numpy() for M in range(2, N + 1)}
     out = npf.cpu().numpy()
     plan.close()
+    if interaction:
+        return out, Ps, {M: Q[M - 2].cpu().numpy() for M in range(2, N + 1)}
     return out, Ps
 
 

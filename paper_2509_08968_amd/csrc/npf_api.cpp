@@ -440,3 +440,59 @@ int run_eager(npf_plan_t plan, const npf_tensor *A, const void *U, const void *V
 }
 
 }  // namespace
+
+extern "C" int npf_run_interaction(npf_plan_t plan, const npf_tensor *A, const void *U,
+                                   const void *V, const void *lambda, void *ws, int64_t ws_bytes,
+                                   void *P_out, void *npf_out, void *inpf_out, void *stream)
+{
+    if (!plan) return fail(NPF_E_INVALID, "null plan");
+    if (!inpf_out) return fail(NPF_E_INVALID, "null interaction output");
+    if (plan->n_out != plan->n)
+        return fail(NPF_E_UNSUPPORTED,
+                    "interaction factors need every mode's P row (zeta* of eq. (9)): no mode subset");
+    // First pass: P_M of every order and the NPF (npf_run checks the remaining arguments).
+    int rc = npf_run(plan, A, U, V, lambda, ws, ws_bytes, P_out, npf_out, stream);
+    if (rc) return rc;
+    // Second pass: the reduction factor becomes zeta* = delta Psi + sum_M P_M, and every
+    // order's last contraction and reduction run again on it (the chain is recomputed: a
+    // later block or order may have overwritten it).
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char *w = static_cast<char *>(ws);
+    {
+        Timed t(plan, "prepare_zeta_star", s);
+        rc = check_hip(launch_prepare(plan, static_cast<const double *>(U),
+                                      static_cast<const double *>(V),
+                                      static_cast<const double *>(lambda), w, s,
+                                      reinterpret_cast<const double *>(w + plan->lay.psum)),
+                       "zeta* staging");
+    }
+    const int64_t nn = plan->n * plan->n;
+    for (int M = 2; M <= plan->N && rc == NPF_OK; ++M) {
+        const OrderLayout ol(plan, M);
+        const bool tucker = tucker_supported(plan, &A[M - 2], M);
+        if (tucker) rc = run_rows(plan, M, &A[M - 2], V, ws, s);
+        double *out = static_cast<double *>(inpf_out) + 2 * (M - 2) * nn;
+        for (int64_t b = 0; b < plan->n_blocks && rc == NPF_OK; ++b) {
+            int64_t j0, J;
+            block_modes(plan, b, j0, J);
+            const BlockShape shape(plan, J);
+            rc = run_chain(plan, M, j0, J, &A[M - 2], U, V, ws, s, tucker);
+            if (rc) break;
+            {
+                Timed t(plan, kname(M, "fused_star"), s);
+                rc = check_hip(launch_fused_last(plan, M, j0, J,
+                                                 static_cast<const double *>(lambda), w, s),
+                               "fused last stage (zeta*)");
+            }
+            if (rc) break;
+            // Phi for the factors of eq. (8); no NPF output in this pass.
+            const NpfOut fin{static_cast<const double *>(U), static_cast<const double *>(V),
+                             nullptr};
+            Timed t(plan, kname(M, "reduce_star"), s);
+            rc = check_hip(launch_reduce_parts(plan, M, j0, J, nullptr, nullptr, false, w, s,
+                                               &fin, out),
+                           "interaction factors");
+        }
+    }
+    return rc;
+}

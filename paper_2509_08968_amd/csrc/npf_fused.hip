@@ -29,12 +29,14 @@ constexpr int64_t kResidentBytes = 128 * 1024;   // LDS budget for resident oper
 // Also the tables of sorted tuples of length 1..N-1 (8 bits per entry), in colex order.
 // With selected modes, also the Psi rows and (when lam is given) the eigenvalues of the
 // computed modes: msel[c*n + k] = Psi[row[c], k] and msel[nc*n + c] = lam[row[c]].
+// With zadd (the sum over orders of P_M, [mode][state]) the reduction's factor becomes the
+// corrected zeta* = delta Psi + zadd of eq. (9) (the interaction factors of eq. (8)).
 __global__ void __launch_bounds__(256)
 prepare(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double delta, int64_t n,
         int64_t npad, int eng, double2 *__restrict__ zeta64, void *__restrict__ phiE,
         void *__restrict__ zetaE, float2 *__restrict__ zeta32, uint64_t *__restrict__ ttab,
         TupleTables tt, const double2 *__restrict__ lam, double2 *__restrict__ msel, int64_t nc,
-        ModeMap mm)
+        ModeMap mm, const double2 *__restrict__ zadd)
 {
     const int64_t N2 = npad * npad;
     const int64_t nsel = msel ? nc * (n + 1) : 0;
@@ -70,6 +72,7 @@ prepare(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double
         const double2 ph = in ? Phi[r * n + c] : make_double2(0.0, 0.0);
         double2 ze = in ? Psi[r * n + c] : make_double2(0.0, 0.0);
         ze = make_double2(delta * ze.x, delta * ze.y);
+        if (zadd && in) ze = add_fp64(ze, zadd[r * n + c]);   // zeta* = zeta + sum_M P_M (eq. (9))
         zeta64[x] = ze;
         zeta32[x] = make_float2(float(ze.x), float(ze.y));
         if (eng == int(Eng::F64)) {
@@ -420,7 +423,8 @@ __global__ void __launch_bounds__(256)
 reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, int64_t J,
              int64_t n, ModeMap mm, double scale, double2 *__restrict__ P,
              double2 *__restrict__ psum, int first, const double2 *__restrict__ Phi,
-             const double2 *__restrict__ Psi, double delta, double2 *__restrict__ npf)
+             const double2 *__restrict__ Psi, double delta, double2 *__restrict__ npf,
+             double2 *__restrict__ inpf)
 {
     __shared__ double2 part[16][16];
     const int64_t per = J * n;
@@ -457,29 +461,38 @@ reduce_parts(const double2 *__restrict__ parts, int64_t nparts, int64_t Jpad, in
             ti *= scale;
             const int64_t jj = e / n, k = e - jj * n;
             const int64_t j = mm.row[jj];
-            P[j * n + k] = make_double2(tr, ti);
-            double2 tot = make_double2(tr, ti);
-            if (!first) {
-                const double2 o = psum[j * n + k];
-                tot = make_double2(o.x + tr, o.y + ti);
-            }
-            psum[j * n + k] = tot;
-            if (npf) {
-                const double2 w = Psi[j * n + k];
-                double2 z = make_double2(delta * w.x, delta * w.y);
-                z = add_fp64(z, tot);
-                npf[k * n + j] = cmul(Phi[k * n + j], z);
-            }
-            if (mm.conj[jj] != kNoRow) {
-                const int64_t jc = mm.conj[jj];
-                const double2 totc = make_double2(tot.x, -tot.y);
-                P[jc * n + k] = make_double2(tr, -ti);
-                psum[jc * n + k] = totc;
+            if (inpf) {
+                // Interaction factor of eq. (8): the sum is -sum_t h[j,t] prod zeta*_k[t_l].
+                inpf[k * n + j] = cmul(Phi[k * n + j], make_double2(-tr, -ti));
+                if (mm.conj[jj] != kNoRow) {
+                    const int64_t jc = mm.conj[jj];
+                    inpf[k * n + jc] = cmul(Phi[k * n + jc], make_double2(-tr, ti));
+                }
+            } else {
+                P[j * n + k] = make_double2(tr, ti);
+                double2 tot = make_double2(tr, ti);
+                if (!first) {
+                    const double2 o = psum[j * n + k];
+                    tot = make_double2(o.x + tr, o.y + ti);
+                }
+                psum[j * n + k] = tot;
                 if (npf) {
-                    const double2 w = Psi[jc * n + k];
+                    const double2 w = Psi[j * n + k];
                     double2 z = make_double2(delta * w.x, delta * w.y);
-                    z = add_fp64(z, totc);
-                    npf[k * n + jc] = cmul(Phi[k * n + jc], z);
+                    z = add_fp64(z, tot);
+                    npf[k * n + j] = cmul(Phi[k * n + j], z);
+                }
+                if (mm.conj[jj] != kNoRow) {
+                    const int64_t jc = mm.conj[jj];
+                    const double2 totc = make_double2(tot.x, -tot.y);
+                    P[jc * n + k] = make_double2(tr, -ti);
+                    psum[jc * n + k] = totc;
+                    if (npf) {
+                        const double2 w = Psi[jc * n + k];
+                        double2 z = make_double2(delta * w.x, delta * w.y);
+                        z = add_fp64(z, totc);
+                        npf[k * n + jc] = cmul(Phi[k * n + jc], z);
+                    }
                 }
             }
         }
@@ -555,7 +568,7 @@ int64_t fused_max_slots(const npf_plan_s *p, int64_t Jpad)
 }
 
 hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V,
-                          const double *lam, char *ws, hipStream_t s)
+                          const double *lam, char *ws, hipStream_t s, const double *zadd)
 {
     const int64_t N2 = p->npad * p->npad;
     char *base = ws + p->lay.phi;
@@ -570,7 +583,8 @@ hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V,
                        reinterpret_cast<uint64_t *>(ws + p->lay.ttab), p->tt,
                        reinterpret_cast<const double2 *>(lam),
                        sel ? reinterpret_cast<double2 *>(ws + p->lay.msel) : nullptr, p->nc,
-                       sel ? mode_map(p, 0, p->nc) : ModeMap{});
+                       sel ? mode_map(p, 0, p->nc) : ModeMap{},
+                       reinterpret_cast<const double2 *>(zadd));
     return hipGetLastError();
 }
 
@@ -613,16 +627,18 @@ int64_t fused_default_groups(const npf_plan_s *p, int M) { return fused_gx(p, p-
 
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
                                double *psum, bool first, char *ws, hipStream_t s,
-                               const NpfOut *fin)
+                               const NpfOut *fin, double *inpf)
 {
     return launch_reduce_parts_n(p, fused_groups(p, M), j0, J, P, psum, first, ws, s, fin,
-                                 p->a_scale[M]);
+                                 p->a_scale[M], inpf);
 }
 
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
                                  double *P, double *psum, bool first, char *ws, hipStream_t s,
-                                 const NpfOut *fin, double scale)
+                                 const NpfOut *fin, double scale, double *inpf)
 {
+    // The interaction factors need Phi; the other mode writes P and the running sum.
+    if (inpf ? (!fin || !fin->V) : (!P || !psum)) return hipErrorInvalidValue;
     const int64_t per = J * p->n;
     int64_t wg = (per + 15) / 16;
     if (wg > 8192) wg = 8192;
@@ -632,7 +648,8 @@ hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0
                        reinterpret_cast<double2 *>(psum), first ? 1 : 0,
                        fin ? reinterpret_cast<const double2 *>(fin->V) : nullptr,
                        fin ? reinterpret_cast<const double2 *>(fin->U) : nullptr, p->prob.delta,
-                       fin ? reinterpret_cast<double2 *>(fin->npf) : nullptr);
+                       fin ? reinterpret_cast<double2 *>(fin->npf) : nullptr,
+                       reinterpret_cast<double2 *>(inpf));
     return hipGetLastError();
 }
 

@@ -210,7 +210,8 @@ hipError_t launch_finalize(const npf_plan_s *p, const double *U, const double *V
 // Operand copies for the MFMA kernels (zero padded, in the plan's precision) and the
 // tuple tables.
 hipError_t launch_prepare(const npf_plan_s *p, const double *U, const double *V,
-                          const double *lam, char *ws, hipStream_t s);
+                          const double *lam, char *ws, hipStream_t s,
+                          const double *zadd = nullptr);
 // Output rows of computed modes [c0, c0 + J).
 ModeMap mode_map(const npf_plan_s *p, int64_t c0, int64_t J);
 // Psi rows and eigenvalue of the computed modes: the staged copies when the plan selects
@@ -227,9 +228,12 @@ struct NpfOut {
     const double *U, *V;      // Psi, Phi
     double *npf;
 };
+// With inpf (interaction pass, eq. (8)): writes inpf[k*n + j] = -Phi[k,j] * (the sum) for
+// the block's modes (and their conjugate fills) and nothing else; fin must then carry Phi
+// (fin->npf may be null).
 hipError_t launch_reduce_parts(const npf_plan_s *p, int M, int64_t j0, int64_t J, double *P,
                                double *psum, bool first, char *ws, hipStream_t s,
-                               const NpfOut *fin = nullptr);
+                               const NpfOut *fin = nullptr, double *inpf = nullptr);
 int64_t fused_groups(const npf_plan_s *p, int M);
 // Most partial-P slots any order writes for a block of Jpad modes.
 int64_t fused_max_slots(const npf_plan_s *p, int64_t Jpad);
@@ -259,7 +263,8 @@ int stage_bf3_tr_tiles(int64_t npad);
 // Partial sums of a block's fused-kernel slots (nparts of them) into P rows and psum.
 hipError_t launch_reduce_parts_n(const npf_plan_s *p, int64_t nparts, int64_t j0, int64_t J,
                                  double *P, double *psum, bool first, char *ws, hipStream_t s,
-                                 const NpfOut *fin = nullptr, double scale = 1.0);
+                                 const NpfOut *fin = nullptr, double scale = 1.0,
+                                 double *inpf = nullptr);
 int64_t fused_default_groups(const npf_plan_s *p, int M);
 bool bf3_tr_fused_supported(const npf_plan_s *p);
 int bf3_items_per_group(int64_t Jpad);
