@@ -13,7 +13,9 @@ Functions follow the paper (arXiv 2509.08968):
   assemble()  Alg. 2 step 20 / eq. (7): NPF[k, i] = Phi[k, i] (delta Psi[i, k] + sum_M P_M[i, k]);
   npf()       orders 2..N of one system, summed and assembled;
   interaction()  eqs. (8)-(9): pNM[k, i] = Phi[k, i] sum_t h_M[i, t] prod_l zeta*_k[t_l] with the
-              corrected zeta*_k = delta Psi[:, k] + sum_M P_M[:, k] (z(0) of eq. (7)).
+              corrected zeta*_k = delta Psi[:, k] + sum_M P_M[:, k] (z(0) of eq. (7));
+  poly_tensor()  derivative tensors of a polynomial vector field at its expansion point (what
+              Alg. 1's numerical Taylor expansion produces from a model).
 """
 from __future__ import annotations
 
@@ -62,10 +64,11 @@ def lib():
             L.npfo_assemble.argtypes = [i64, P, P, dbl, P, P]
             L.npfo_sym_z.argtypes = [i64, i32, P, P, P, P, dbl, P, P, i64, P, i32]
             L.npfo_full_z.argtypes = [i64, i32, P, P, P, P, dbl, P, P]
+            L.npfo_poly_tensor.argtypes = [i64, i32, i64, P, P, P, i32, P, P]
             L.npfo_binom.argtypes = [i64, i64]
             L.npfo_binom.restype = i64
             for f in (L.npfo_full, L.npfo_sym, L.npfo_sym_hash, L.npfo_assemble, L.npfo_sym_z,
-                      L.npfo_full_z):
+                      L.npfo_full_z, L.npfo_poly_tensor):
                 f.restype = ctypes.c_int
             _lib = L
     return _lib
@@ -242,4 +245,21 @@ def interaction(sys, Ps=None, modes=None, method: str = "sym", nthreads: int = 0
     for M in sys.orders:
         Q = reduce_with(sys, M, Z, modes=cols, method=method, nthreads=nthreads)
         out[M] = _c128(sys.V)[:, cols] * (-Q).T
+    return out
+
+
+def poly_tensor(field, n: int, M: int) -> np.ndarray:
+    """Derivative tensor A_M [n, binom(n+M-1, M)] of a polynomial vector field at its
+    expansion point (dict with eq, coef, var [terms, maxdeg], x_eq or None), from the binomial
+    expansion of every monomial (npfo_poly_tensor)."""
+    L = lib()
+    eq = np.ascontiguousarray(field["eq"], np.int32)
+    coef = np.ascontiguousarray(field["coef"], np.float64)
+    var = np.ascontiguousarray(field["var"], np.int32)
+    x_eq = None if field.get("x_eq") is None else np.ascontiguousarray(field["x_eq"], np.float64)
+    out = np.empty((n, _binom(n + M - 1, M)))
+    rc = L.npfo_poly_tensor(n, M, len(eq), _p(eq), _p(coef), _p(var), var.shape[1], _p(x_eq),
+                            _p(out))
+    if rc != 0:
+        raise ValueError("npfo_poly_tensor rejected its arguments")
     return out

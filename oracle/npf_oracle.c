@@ -421,3 +421,62 @@ int npfo_assemble(int64_t n, const npfo_c *Phi, const npfo_c *Psi, double delta,
         }
     return 0;
 }
+
+/* ------------------------------------------------------------------ derivative tensors
+ * The M-th derivative tensor of a polynomial vector field at the expansion point x* (the
+ * tensors the numerical Taylor expansion of Alg. 1 produces from the model): for each term
+ * c * prod_v x_v^{e_v} of equation k, x = x* + y gives
+ *   c * prod_v sum_{j_v} binom(e_v, j_v) x*_v^{e_v - j_v} y_v^{j_v},
+ * whose part of total degree M in y, sum_v j_v = M, contributes
+ *   c * prod_v binom(e_v, j_v) x*_v^{e_v - j_v} * prod_v j_v!
+ * to the derivative d^M f_k / dy_{a_1} .. dy_{a_M} for the sorted tuple a holding each
+ * variable v j_v times (differentiating prod_v y_v^{j_v} once by each of those variables
+ * leaves prod_v j_v!).  Terms: eq[q], coef[q], var[q*maxdeg + i] (the monomial's variables
+ * with repetition, padded with -1).  out[k*U + rank(a)], zeroed first. */
+int npfo_poly_tensor(int64_t n, int M, int64_t n_terms, const int32_t *eq, const double *coef,
+                     const int32_t *var, int maxdeg, const double *x_eq, double *out)
+{
+    if (n < 1 || M < 1 || M > 8 || maxdeg < 0 || maxdeg > 8 || (n_terms > 0 && (!eq || !coef || !var))
+        || !out)
+        return -1;
+    const int64_t U = npfo_binom(n + M - 1, M);
+    for (int64_t x = 0; x < n * U; ++x) out[x] = 0.0;
+    for (int64_t q = 0; q < n_terms; ++q) {
+        /* distinct variables of the monomial and their exponents */
+        int32_t v[8], e[8];
+        int nv = 0;
+        for (int i = 0; i < maxdeg; ++i) {
+            const int32_t a = var[q * maxdeg + i];
+            if (a < 0) continue;
+            if (a >= n) return -1;
+            int f = -1;
+            for (int l = 0; l < nv; ++l) if (v[l] == a) f = l;
+            if (f < 0) { v[nv] = a; e[nv] = 1; ++nv; } else e[f] += 1;
+        }
+        if (eq[q] < 0 || eq[q] >= n) return -1;
+        /* every split j_l <= e_l with sum_l j_l = M */
+        int32_t j[8] = {0};
+        for (;;) {
+            int tot = 0;
+            for (int l = 0; l < nv; ++l) tot += j[l];
+            if (tot == M) {
+                double w = coef[q];
+                int32_t t[8];
+                int m = 0;
+                for (int l = 0; l < nv; ++l) {
+                    w *= (double)npfo_binom(e[l], j[l]) * factorial(j[l]);
+                    const double xs = x_eq ? x_eq[v[l]] : 0.0;
+                    for (int r = 0; r < e[l] - j[l]; ++r) w *= xs;
+                    for (int r = 0; r < j[l]; ++r) t[m++] = v[l];
+                }
+                sort_small(t, M);
+                out[(int64_t)eq[q] * U + npfo_rank(t, M)] += w;
+            }
+            int l = 0;                          /* next split (odometer over j_l <= e_l) */
+            while (l < nv && j[l] == e[l]) { j[l] = 0; ++l; }
+            if (l == nv) break;
+            j[l] += 1;
+        }
+    }
+    return 0;
+}

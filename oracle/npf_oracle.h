@@ -88,6 +88,14 @@ int npfo_sym_hash(int64_t n, int M, const npfo_c *lam, const npfo_c *Phi, const 
 int npfo_assemble(int64_t n, const npfo_c *Phi, const npfo_c *Psi, double delta,
                   const npfo_c *Psum, npfo_c *npf);
 
+/* The M-th derivative tensor, packed over sorted tuples, of the polynomial vector field
+ * f_k(x) = sum_{terms q of equation k} coef[q] prod_i x_{var[q*maxdeg + i]} (variables with
+ * repetition, -1 = none) at the expansion point x_eq (NULL = 0): out[k*U_M + rank(a)] =
+ * d^M f_k / dx_{a_1} .. dx_{a_M} at x_eq, from the binomial expansion of every monomial --
+ * the tensors Alg. 1 obtains by numerical Taylor expansion of the model. */
+int npfo_poly_tensor(int64_t n, int M, int64_t n_terms, const int32_t *eq, const double *coef,
+                     const int32_t *var, int maxdeg, const double *x_eq, double *out);
+
 #ifdef __cplusplus
 }
 #endif

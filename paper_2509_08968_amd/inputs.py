@@ -286,6 +286,38 @@ def clamp_system(n: int, orders, seed: int, eps: float = CLAMP_EPS, name: str = 
     return _finish(name, n, lam, V, A, {M: None for M in A}, eps=eps, **kw)
 
 
+def poly_field(n: int, orders, seed: int, terms_per_eq: int = 6, max_degree: int = None,
+               x_eq=None, scale: float = 0.5, spectrum_seed: int = None):
+    """A sparse polynomial vector field x' = f(x) with f(0) = 0: the linear part is the
+    Jacobian A1 = Re(V diag(lam) V^-1) of a seeded spectrum (as for the other systems), and
+    every equation k gets ``terms_per_eq`` monomials of each degree in ``orders`` over
+    seeded variables (with repetition), coefficients N(0, 1) * scale^degree.  Returns the
+    terms as arrays (eq [T], coef [T], var [T, D] padded with -1, D = max degree) sorted by
+    equation, the CSR offsets eq_ptr [n+1], the expansion point x_eq (None = 0) and the
+    spectrum (lam, V, U = V^-1)."""
+    rng = np.random.default_rng(seed)
+    lam = _spectrum(n, rng)
+    V = _eigvecs(n, rng)
+    U = np.linalg.inv(V)
+    A1 = np.real(V @ np.diag(lam) @ U)
+    D = max(max(orders), 1) if max_degree is None else max_degree
+    eq, coef, var = [], [], []
+    for k in range(n):
+        for a in range(n):
+            eq.append(k); coef.append(A1[k, a]); var.append([a] + [-1] * (D - 1))
+        for d in sorted(orders):
+            for _ in range(terms_per_eq):
+                vs = sorted(int(x) for x in rng.integers(0, n, d))
+                eq.append(k); coef.append(rng.standard_normal() * scale ** d)
+                var.append(vs + [-1] * (D - d))
+    eq = np.asarray(eq, np.int32)
+    eq_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(eq, minlength=n), out=eq_ptr[1:])
+    return {"n": n, "eq": eq, "coef": np.asarray(coef), "var": np.asarray(var, np.int32),
+            "eq_ptr": eq_ptr, "x_eq": None if x_eq is None else np.asarray(x_eq, np.float64),
+            "lam": lam, "V": V, "U": U, "A1": A1}
+
+
 # ----------------------------------------------------------------------------- hash tensors
 SPLITMIX_GAMMA = 0x9E3779B97F4A7C15
 HASH_SQRT3 = 1.7320508075688772

@@ -445,3 +445,64 @@ def test_p12_interaction_factor_scales_as_delta_power():
         dev.append(rel(b, a * 0.5 ** 3))
     assert dev[1] < 1e-7
     assert 80 < dev[0] / dev[1] < 120, dev
+
+
+# ------------------------------------------------------------------ derivative tensors (Alg. 1)
+def _field_eval(field, x):
+    """f(x) of a polynomial vector field, term by term (numpy)."""
+    out = np.zeros(field["n"])
+    for k, c, vs in zip(field["eq"], field["coef"], field["var"]):
+        out[k] += c * np.prod([x[v] for v in vs if v >= 0])
+    return out
+
+
+def test_p13_poly_tensor_closed_forms():
+    """f_0 = 3 x_1^2 x_2: at 0 the only third derivative is d^3/dx1 dx1 dx2 = 6; at
+    x* = (0, 2, 0.5) the second-order part 3 (2 + y1)^2 (0.5 + y2) -> 1.5 y1^2 + 12 y1 y2 gives
+    d^2/dx1^2 = 3 and d^2/dx1 dx2 = 12."""
+    field = {"n": 3, "eq": np.array([0], np.int32), "coef": np.array([3.0]),
+             "var": np.array([[1, 1, 2]], np.int32), "x_eq": None}
+    A3 = oracle.poly_tensor(field, 3, 3)
+    want = np.zeros_like(A3)
+    want[0, I.colex_rank((1, 1, 2))] = 6.0
+    assert np.array_equal(A3, want)
+    field["x_eq"] = np.array([0.0, 2.0, 0.5])
+    A2 = oracle.poly_tensor(field, 3, 2)
+    want = np.zeros_like(A2)
+    want[0, I.colex_rank((1, 1))] = 3.0
+    want[0, I.colex_rank((1, 2))] = 12.0
+    assert np.allclose(A2, want, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+def test_p13_poly_tensor_polarization(M):
+    """With only linear and degree-M terms, polarization of the field evaluated term by term
+    is exact: A_M[k, t] = sum_{S} (-1)^(M-|S|) f_k(sum_{i in S} e_{t_i})."""
+    field = I.poly_field(5, [M], 1300 + M, terms_per_eq=4)
+    A = oracle.poly_tensor(field, 5, M)
+    for r, t in enumerate(I.sorted_tuples(5, M)):
+        acc = np.zeros(5)
+        for size in range(1, M + 1):
+            for S in itertools.combinations(range(M), size):
+                y = np.zeros(5)
+                for i in S:
+                    y[t[i]] += 1.0
+                acc += (-1) ** (M - size) * _field_eval(field, y)
+        assert np.allclose(A[:, r], acc, rtol=1e-12, atol=1e-12), t
+
+
+def test_p13_poly_tensor_taylor_expansion_at_equilibrium():
+    """At an expansion point x* != 0 the tensors of every order reproduce the field exactly:
+    f(x* + y) - f(x*) = sum_{M=1..D} (1/M!) sum_{t sorted} m(t) A_M[:, t] prod_i y_{t_i}."""
+    rng = np.random.default_rng(14)
+    n, D = 4, 4
+    field = I.poly_field(n, [2, 3, 4], 1310, terms_per_eq=5, x_eq=rng.standard_normal(n) * 0.5)
+    y = rng.standard_normal(n) * 0.3
+    lhs = _field_eval(field, field["x_eq"] + y) - _field_eval(field, field["x_eq"])
+    rhs = np.zeros(n)
+    for M in range(1, D + 1):
+        A = oracle.poly_tensor(field, n, M)
+        tups = I.sorted_tuples(n, M)
+        mult = _multiplicities(tups)
+        rhs += (A * (mult * np.prod(y[tups], axis=1))).sum(axis=1) / math.factorial(M)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-13)
