@@ -283,6 +283,36 @@ int npf_batch_time(npf_batch_t batch, const npf_tensor *A, const void *const *U,
 int npf_hash_fill(int64_t n, int32_t order, uint64_t seed, double scale, int64_t k0,
                   int64_t k1, double *out, void *stream);
 
+/* A polynomial vector field x' = f(x), term by term (device memory, caller owned): term q
+ * is coef[q] * prod_i x_{var[q*max_degree + i]} over the entries of var that are >= 0
+ * (variables with repetition, padded with negative values); the terms of equation k are
+ * eq_ptr[k] .. eq_ptr[k+1]-1 (eq_ptr has n + 1 entries, non-decreasing; values outside
+ * [0, n_terms] are clamped).  x_eq is the expansion point x* [n], NULL for the origin. */
+typedef struct npf_poly {
+    int64_t n_terms;
+    const int64_t *eq_ptr;
+    const double *coef;
+    const int32_t *var;
+    int32_t max_degree;        /* 1..8 entries of var per term                        */
+    int32_t reserved;
+    const double *x_eq;
+} npf_poly;
+
+/* The numerical Taylor expansion of Alg. 1 (Section II-B) on the device: rows [k0, k1) of
+ * the M-th derivative tensor of the field at x*, out[(k - k0)*U_M + r] (device, FP64,
+ * caller owned) = d^M f_k / dx_{t_1} .. dx_{t_M} at x* for the sorted tuple t of colex
+ * rank r, U_M = binom(n + order - 1, order): the convention NPF_A_DERIVATIVE, ready for
+ * npf_run as an NPF_SRC_DENSE tensor (order 1 gives the Jacobian).  Each entry comes from
+ * values of the field's terms at x* + s y_S, y_S the sums of the unit vectors of the
+ * subsets S of t: the alternating sum over S (polarization) and Lagrange extraction of
+ * the s^M coefficient are exact for polynomials, so only rounding separates the result
+ * from the derivative.  A row with a variable >= n reads NaN.  Asynchronous on `stream`.
+ * Errors: NPF_E_INVALID for a null poly, n < 1, order outside [1, NPF_MAX_ORDER],
+ * max_degree outside [1, 8], n_terms < 0, a bad row range, U_M >= 2^40, or null arrays
+ * where rows or terms are to be read or written. */
+int npf_taylor_fill(int64_t n, int32_t order, const npf_poly *poly, int64_t k0, int64_t k1,
+                    double *out, void *stream);
+
 /* Alg. 2 step 20: NPF[k*n + i] = Phi[k,i] (delta Psi[i,k] + P_sum[i*n + k]).
  * P_sum may be NULL (the linear participation factors). */
 int npf_finalize(npf_plan_t plan, const void *U, const void *V, const void *P_sum,

@@ -7,6 +7,7 @@ GPU; loading the library fails loudly if it has not been built.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass, field
 from typing import Dict, List, Optional
@@ -28,7 +29,7 @@ EXPORTED = [
     "npf_plan_profile", "npf_plan_kernel_times", "npf_error_string", "npf_last_error",
     "npf_hash_fill", "npf_batch_create", "npf_batch_info", "npf_batch_destroy",
     "npf_batch_run", "npf_batch_tune", "npf_batch_launches", "npf_batch_time",
-    "npf_plan_modes", "npf_run_static", "npf_run_interaction",
+    "npf_plan_modes", "npf_run_static", "npf_run_interaction", "npf_taylor_fill",
 ]
 A_DERIVATIVE, A_TAYLOR = 0, 1
 
@@ -46,6 +47,14 @@ class NpfTensor(ctypes.Structure):
         ("col_ptr", ctypes.c_void_p), ("row_k", ctypes.c_void_p),
         ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
         ("seed", ctypes.c_uint64), ("scale", ctypes.c_double),
+    ]
+
+
+class NpfPoly(ctypes.Structure):
+    _fields_ = [
+        ("n_terms", ctypes.c_int64), ("eq_ptr", ctypes.c_void_p), ("coef", ctypes.c_void_p),
+        ("var", ctypes.c_void_p), ("max_degree", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("x_eq", ctypes.c_void_p),
     ]
 
 
@@ -125,6 +134,7 @@ def lib():
         L.npf_plan_kernel_times.argtypes = [P, ctypes.POINTER(NpfKernelTime), i32,
                                             ctypes.POINTER(i32)]
         L.npf_hash_fill.argtypes = [i64, i32, ctypes.c_uint64, dbl, i64, i64, P, P]
+        L.npf_taylor_fill.argtypes = [i64, i32, ctypes.POINTER(NpfPoly), i64, i64, P, P]
         PP = ctypes.POINTER(P)
         L.npf_batch_create.argtypes = [ctypes.POINTER(NpfProblem), i64, i64, ctypes.POINTER(P)]
         L.npf_batch_info.argtypes = [P, ctypes.POINTER(NpfBatchReport)]
@@ -144,7 +154,7 @@ def lib():
                   "npf_plan_kernel_times", "npf_hash_fill", "npf_batch_create",
                   "npf_batch_info", "npf_batch_run", "npf_batch_tune", "npf_batch_launches",
                   "npf_batch_time", "npf_plan_modes", "npf_run_static",
-                  "npf_run_interaction"):
+                  "npf_run_interaction", "npf_taylor_fill"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -374,6 +384,50 @@ def hash_fill(n: int, order: int, seed: int, scale: float, k0: int, k1: int, out
     tensor ``out`` (at least (k1 - k0) * binom(n + order - 1, order) elements)."""
     _check(lib().npf_hash_fill(n, order, int(seed), float(scale), k0, k1, _ptr(out),
                                _stream(stream)), "npf_hash_fill")
+
+
+class DevicePoly:
+    """A polynomial vector field in device memory (the npf_poly arrays), from a dict with
+    eq_ptr [n+1], coef [T], var [T, D] (padded with -1) and x_eq ([n] or None)."""
+
+    def __init__(self, terms, device):
+        import torch
+        var = np.ascontiguousarray(terms["var"], np.int32)
+        self.n = int(terms["n"])
+        self.t = {
+            "eq_ptr": torch.from_numpy(np.ascontiguousarray(terms["eq_ptr"], np.int64)).to(device),
+            "coef": torch.from_numpy(_at_least_one(np.ascontiguousarray(terms["coef"], np.float64))).to(device),
+            "var": torch.from_numpy(_at_least_one(var.reshape(-1))).to(device),
+        }
+        x_eq = terms.get("x_eq")
+        if x_eq is not None:
+            self.t["x_eq"] = torch.from_numpy(np.ascontiguousarray(x_eq, np.float64)).to(device)
+        self.desc = NpfPoly(len(terms["coef"]), self.t["eq_ptr"].data_ptr(), self.t["coef"].data_ptr(),
+                            self.t["var"].data_ptr(), var.shape[1], 0,
+                            self.t["x_eq"].data_ptr() if x_eq is not None else None)
+
+
+def taylor_fill(poly: DevicePoly, order: int, k0: int, k1: int, out, stream=None):
+    """npf_taylor_fill: rows [k0, k1) of the order-th derivative tensor of the field at its
+    expansion point into the float64 device tensor ``out`` (at least
+    (k1 - k0) * binom(n + order - 1, order) elements)."""
+    _check(lib().npf_taylor_fill(poly.n, order, ctypes.byref(poly.desc), k0, k1, _ptr(out),
+                                 _stream(stream)), "npf_taylor_fill")
+
+
+def taylor_tensor(poly: DevicePoly, order: int, device="cuda:0", batch_rows: int = 0) -> DeviceTensor:
+    """The order-th derivative tensor of the field, filled on the device in batches of
+    ``batch_rows`` rows (0 = one batch) as a dense tensor descriptor for the hot path."""
+    import torch
+    n = poly.n
+    UM = math.comb(n + order - 1, order)
+    vals = torch.empty(n * UM, dtype=torch.float64, device=device)
+    step = batch_rows or n
+    for k0 in range(0, n, step):
+        k1 = min(n, k0 + step)
+        taylor_fill(poly, order, k0, k1, vals[k0 * UM:k1 * UM])
+    desc = NpfTensor(SRC_DENSE, order, vals.data_ptr(), None, None, None, 0, 0)
+    return DeviceTensor(order, SRC_DENSE, {"values": vals}, desc)
 
 
 @dataclass
