@@ -46,6 +46,12 @@ MUTANTS = {
                                   "const int64_t last = 0;"),
     "full sum skips a lower index": ("for (int i = 1; i < M; ++i) z = z * zeta_at(Z, Psi, delta, n, digits[i], k);",
                                      "for (int i = 2; i < M; ++i) z = z * zeta_at(Z, Psi, delta, n, digits[i], k);"),
+    "Taylor drops the binomial": ("w *= (double)npfo_binom(e[l], j[l]) * factorial(j[l]);",
+                                  "w *= factorial(j[l]);"),
+    "Taylor drops the factorial": ("w *= (double)npfo_binom(e[l], j[l]) * factorial(j[l]);",
+                                   "w *= (double)npfo_binom(e[l], j[l]);"),
+    "Taylor power of x* off by one": ("for (int r = 0; r < e[l] - j[l]; ++r) w *= xs;",
+                                      "for (int r = 1; r < e[l] - j[l]; ++r) w *= xs;"),
 }
 
 PIN_CALLS = [
@@ -63,6 +69,9 @@ PIN_CALLS = [
     lambda: pins.test_clamp_exact_resonance(),
     lambda: pins.test_p11_interaction_full_equals_sym(4, 2),
     lambda: pins.test_p12_interaction_factors_reconstruct_the_kick([2], 3),
+    lambda: pins.test_p13_poly_tensor_closed_forms(),
+    lambda: pins.test_p13_poly_tensor_polarization(3),
+    lambda: pins.test_p13_poly_tensor_taylor_expansion_at_equilibrium(),
 ]
 
 
