@@ -28,13 +28,14 @@ import sys
 from collections import defaultdict
 
 
-def launch_names(workload: str, precision: str, budget: int = 0):
-    """Kernel names of one npf_run step, in dispatch order."""
+def launch_names(workload: str, precision: str, budget: int = 0, conj: bool = True):
+    """Kernel names of one npf_run step, in dispatch order, for the plan bench.py makes
+    (one mode of each conjugate pair computed unless ``conj`` is False)."""
     from paper_2509_08968_amd import binding as B
     from paper_2509_08968_amd import inputs as I
     s = I.WORKLOADS[workload]()
     plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
-                  support_max=s.support_max)
+                  support_max=s.support_max, conj_of=B.conj_pairs(s.lam) if conj else None)
     # Graph replays of single-block plans with several orders run the orders concurrently;
     # their dispatch order is the capture order: every order's launches, highest order first,
     # then the partial sums of every order in ascending order (the workloads here fit the
@@ -73,7 +74,7 @@ def batch_launch_names(workload: str):
     in _multi); the per-system launches around them are not named here.  The launch records
     are listed by wave, padded size, order and stage; a run launches them by wave, order and
     stage (the fused last stage after stage M-1), each over the padded sizes in turn."""
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import bench
     from paper_2509_08968_amd import binding as B
     from paper_2509_08968_amd import inputs as I
@@ -148,7 +149,7 @@ def write_trace(workload, precision, stats_csv, out_dir, cmd):
 
 def write_traffic(workload, precision, fetch_csv, write_csv, copy_mib, out_dir, cmds):
     """HBM traffic summary and the per-launch JSON that bench.py reads."""
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import bench
     budget = bench.budget_for(workload, precision)
     t = traffic(workload, precision, fetch_csv, write_csv, float(copy_mib), budget)
@@ -224,7 +225,7 @@ def main(argv):
         write_traffic(workload, precision, fetch_csv, write_csv, copy_mib, out_dir, argv[7:])
     elif mode == "sq":
         workload, precision, csv_path, out_dir, cmd = argv[1:6]
-        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
         import bench
         write_sq(workload, precision, csv_path, out_dir, cmd, bench.budget_for(workload, precision))
     else:

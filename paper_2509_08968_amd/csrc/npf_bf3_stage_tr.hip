@@ -372,6 +372,11 @@ stage_bf3_sl(Bf3Args a)
                     split_x(ring[kc % PD], xr, xi);
                     if (kc + PD < KC) load_chunk(src, rows, kc + PD, ring[kc % PD]);
                     else if (nval) load_chunk(nsrc, nrows, kc + PD - KC, ring[kc % PD]);
+                    // Issue the gathers before this chunk's products: left to itself the
+                    // scheduler sinks them below the MFMAs, and the next chunk then waits
+                    // for memory with no work in between.  (Not at 160 and 256 states, where
+                    // the pinned order needs more registers than a wave has.)
+                    if constexpr (NP != 160 && NP != 256) __builtin_amdgcn_sched_barrier(0);
                     const Split3 xng = negx3(xi);
 #pragma unroll
                     for (int tt = T0; tt < TT; ++tt) {
