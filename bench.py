@@ -383,34 +383,58 @@ def bench_batch(args):
                 "executed_mfma_frac": achieved * SPLIT_PRODUCTS["bf16x3"] / PEAK_TFLOPS["bf16x3"],
                 "timing": "HIP events around every shared launch, one eager run"}
 
-    # Per-system rates: each system alone through npf_run (eager launches), same precision.
+    # Per-system runs: each system alone through npf_run -- split-BF16 with eager launches
+    # and replayed graphs, and plain FP64 (replayed graphs) as the batched path's baseline.
     solo = None
     if not args.no_solo:
-        big = max(B.Plan(s.n, s.order_max, "bf16x3", support_max=s.support_max).workspace_bytes
-                  for s in ss)
         del ws
         torch.cuda.empty_cache()
-        wsolo = torch.empty(big, dtype=torch.uint8, device=device)
-        rates, total = [], 0.0
-        for q, s in enumerate(ss):
-            plan = B.Plan(s.n, s.order_max, "bf16x3", s.eps, s.tau, s.delta,
-                          support_max=s.support_max, graph=False)
-            plan.run(devs[q].tensors, devs[q].U, devs[q].V, devs[q].lam, wsolo, P[q], N[q], st)
-            a, c = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(st)
-            for _ in range(3):
+
+        def solo_leg(prec, graph):
+            big = max(B.Plan(s.n, s.order_max, prec, support_max=s.support_max).workspace_bytes
+                      for s in ss)
+            wsolo = torch.empty(big, dtype=torch.uint8, device=device)
+            rates, total = [], 0.0
+            for q, s in enumerate(ss):
+                plan = B.Plan(s.n, s.order_max, prec, s.eps, s.tau, s.delta,
+                              support_max=s.support_max, graph=graph)
                 plan.run(devs[q].tensors, devs[q].U, devs[q].V, devs[q].lam, wsolo, P[q], N[q], st)
-            c.record(st)
-            torch.cuda.synchronize()
-            t = a.elapsed_time(c) / 3
-            total += t
-            rates.append(plan.modal_entries / (t * 1e-3))
-            plan.close()
-        rates = np.asarray(rates)
-        solo = {"launches": "eager (no graph)", "sum_ms": total, "batching_speedup": total / ms,
-                "entries_per_s_min": float(rates.min()), "entries_per_s_median": float(np.median(rates)),
-                "entries_per_s_max": float(rates.max())}
-        log(f"[bench] solo: sum {total:.3f} ms, batching speedup {total / ms:.2f}x")
+                a, c = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(st)
+                for _ in range(3):
+                    plan.run(devs[q].tensors, devs[q].U, devs[q].V, devs[q].lam, wsolo, P[q], N[q], st)
+                c.record(st)
+                torch.cuda.synchronize()
+                t = a.elapsed_time(c) / 3
+                total += t
+                rates.append(plan.modal_entries / (t * 1e-3))
+                plan.close()
+            del wsolo
+            torch.cuda.empty_cache()
+            rates = np.asarray(rates)
+            return {"sum_ms": total, "batch_speedup": total / ms,
+                    "entries_per_s_min": float(rates.min()),
+                    "entries_per_s_median": float(np.median(rates)),
+                    "entries_per_s_max": float(rates.max())}
+
+        solo = {"bf16x3_eager": solo_leg("bf16x3", False), "bf16x3_graph": solo_leg("bf16x3", True)}
+        solo["batching_speedup"] = solo["bf16x3_eager"]["batch_speedup"]
+        fp64 = solo_leg("fp64", True)
+        e64 = {}
+        for q in picks:                     # the FP64 results of the sampled systems
+            s = ss[q]
+            modes = sorted({0, s.n // 2 + 1, s.n - 1})
+            for M in s.orders:
+                e = err_summary(P[q][M - 2].cpu().numpy()[modes],
+                                oracle.sym(s, M, modes=modes)["P"])
+                cur = e64.setdefault(f"P{M}", {k: 0.0 for k in e})
+                for k, v in e.items():
+                    cur[k] = max(cur[k], v)
+        fp64["rel_err"] = e64
+        solo["fp64_graph"] = fp64
+        log(f"[bench] solo: bf16x3 eager {solo['bf16x3_eager']['sum_ms']:.3f} ms, graph "
+            f"{solo['bf16x3_graph']['sum_ms']:.3f} ms, fp64 graph {fp64['sum_ms']:.3f} ms; "
+            f"batch {ms:.3f} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
