@@ -473,6 +473,89 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def interaction_leg(s, sysm, precision, budget, conj, device, refP, modes):
+    """npf_run_interaction on the workload (the NPFs and the interaction factors of
+    eqs. (8)-(9), two passes of the chain): one warm call, one timed call; errors against the
+    oracle when the reference holds every mode's P (n <= 64)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2509_08968_amd import binding as B
+    n, N = s.n, s.order_max
+    plan = B.Plan(n, N, precision, s.eps, s.tau, s.delta, budget_bytes=budget,
+                  support_max=s.support_max, conj_of=B.conj_pairs(s.lam) if conj else None)
+    ws = plan.workspace(device)
+    Q = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
+    P = torch.empty((N - 1, n, n), dtype=torch.complex128, device=device)
+    npf = torch.empty((n, n), dtype=torch.complex128, device=device)
+    st = torch.cuda.Stream(device=device)
+    plan.run_interaction(sysm.tensors, sysm.U, sysm.V, sysm.lam, ws, Q, P, npf, st)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    plan.run_interaction(sysm.tensors, sysm.U, sysm.V, sysm.lam, ws, Q, P, npf, st)
+    e1.record(st)
+    torch.cuda.synchronize()
+    out = {"ms_per_step": e0.elapsed_time(e1), "passes": 2,
+           "modal_entries_per_pass": plan.modal_entries, "timing": "one eager call after a warm one"}
+    if len(modes) == n:
+        ref = oracle.interaction(s, Ps={M: np.asarray(refP[M]) for M in s.orders})
+        out["rel_err"] = {f"p{M}": err_summary(Q[M - 2].cpu().numpy().T, ref[M].T)
+                          for M in s.orders}
+    else:
+        out["rel_err"] = None
+        out["parity"] = "tests/test_gpu_interaction.py (the oracle needs every mode's P)"
+    plan.close()
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def taylor_leg(device, n=200):
+    """npf_taylor_fill (the numerical Taylor expansion of Alg. 1 on the device) for a seeded
+    polynomial field of n states with terms of degrees 1-4 about a nonzero x*: all rows of
+    A_3 (checked element by element against the oracle's binomial expansion) and a 16-row
+    batch of A_4, each timed over three calls after a warm one."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2509_08968_amd import binding as B
+    from paper_2509_08968_amd import inputs as I
+    rng = np.random.default_rng(I.BASE_SEED + 77)
+    field = I.poly_field(n, [2, 3, 4], I.BASE_SEED + 78, terms_per_eq=6,
+                         x_eq=rng.standard_normal(n) * 0.3)
+    poly = B.DevicePoly(field, device)
+    st = torch.cuda.Stream(device=device)
+    res = {"n": n, "terms": int(len(field["coef"])), "max_degree": 4}
+    for M, rows in ((3, n), (4, 16)):
+        UM = math.comb(n + M - 1, M)
+        buf = torch.empty(rows * UM, dtype=torch.float64, device=device)
+        B.taylor_fill(poly, M, 0, rows, buf, st)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(3):
+            B.taylor_fill(poly, M, 0, rows, buf, st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        r = {"rows": rows, "entries": rows * UM, "ms_per_call": ms,
+             "entries_per_s": rows * UM / (ms * 1e-3),
+             "write_GBps": 8 * rows * UM / (ms * 1e-3) / 1e9}
+        r["write_frac_of_hbm_peak"] = r["write_GBps"] / HBM_GBPS
+        if M == 3:
+            ref = oracle.poly_tensor(field, n, M)
+            got = buf.cpu().numpy().reshape(rows, UM)
+            r["max_abs_err_over_max"] = float(np.abs(got - ref).max() / max(1.0, np.abs(ref).max()))
+            del ref, got
+        res[f"A{M}"] = r
+        del buf
+        torch.cuda.empty_cache()
+    return res
+
+
 DEFAULT_WORKLOAD = "n200-o4-dense-hash"
 
 
@@ -499,6 +582,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the interaction-factor and derivative-tensor legs")
     ap.add_argument("--profile-steps", type=int, default=2,
                     help="eager steps with an event pair around every kernel (0: none)")
     ap.add_argument("--no-profile", action="store_true")
@@ -587,6 +672,15 @@ def main():
     legs = {p: leg(p) for p in ("fp32", "fp64")
             if p != args.precision and not getattr(args, f"no_{p}")}
 
+    inter = taylor = None
+    if not args.no_next:
+        torch.cuda.empty_cache()
+        inter = interaction_leg(s, sysm, args.precision, budget_for(args.workload, args.precision),
+                                conj, device, refP, modes)
+        log(f"[bench] interaction factors: {inter['ms_per_step']:.3f} ms, err {inter['rel_err']}")
+        taylor = taylor_leg(device)
+        log(f"[bench] derivative tensors: {taylor}")
+
     roof = None
     if res["kernels"]:
         psteps = res["profile_steps"]
@@ -631,6 +725,8 @@ def main():
         "rel_err_vs_oracle": err,
         "fp64_gpu": legs.get("fp64"),
         "fp32_gpu": legs.get("fp32"),
+        "interaction_factors": inter,
+        "derivative_tensors": taylor,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

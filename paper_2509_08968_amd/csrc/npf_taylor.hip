@@ -52,64 +52,115 @@ __device__ __forceinline__ double node_weight(int e, int m, int M)
     return num / den;
 }
 
+// One workgroup per (row k, range of kTaylorThreads ranks).  The row's terms are read in
+// rounds of kTaylorThreads, one per thread; the ones that can contribute (degree >= M, and at
+// x* = 0 degree exactly M) are compacted into LDS in their original order -- a prefix sum of
+// the per-wave ballots, so the order of the sums is fixed -- and every thread then evaluates
+// its entry over them.
 template <int M>
 __global__ __launch_bounds__(kTaylorThreads) void taylor_fill(
     int64_t n, int64_t k0, int64_t rows, int64_t UM, const int64_t *__restrict__ eq_ptr,
     int64_t n_terms, const double *__restrict__ coef, const int32_t *__restrict__ var, int D,
     const double *__restrict__ x_eq, double *__restrict__ out)
 {
+    constexpr int NW = kTaylorThreads / 64;
+    __shared__ double s_coef[kTaylorThreads];
+    __shared__ int32_t s_var[kTaylorThreads][kMaxDegree];
+    __shared__ int32_t s_deg[kTaylorThreads];
+    __shared__ int s_wcnt[NW];
+    __shared__ int s_bad;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r = int64_t(blockIdx.x) * kTaylorThreads + threadIdx.x;
+    const bool live = r < UM;
+    int32_t t[M];
+    if (live) colex_unrank(r, M, n, t);
+    else
+        for (int l = 0; l < M; ++l) t[l] = 0;
     for (int64_t kr = blockIdx.y; kr < rows; kr += gridDim.y) {
         const int64_t k = k0 + kr;
         int64_t q0 = eq_ptr[k], q1 = eq_ptr[k + 1];
         q0 = q0 < 0 ? 0 : (q0 > n_terms ? n_terms : q0);
         q1 = q1 < q0 ? q0 : (q1 > n_terms ? n_terms : q1);
-        for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < UM;
-             r += int64_t(gridDim.x) * blockDim.x) {
-            int32_t t[M];
-            colex_unrank(r, M, n, t);
-            double acc = 0.0;
-            bool bad = false;
-            for (int64_t q = q0; q < q1; ++q) {
-                // The term's variables (with repetition) and, per variable, the positions of
-                // t that hold it as a bit mask: y_S of that variable is popcount(mask & S).
-                int32_t a[kMaxDegree];
-                unsigned pos[kMaxDegree];
-                int d = 0;
-                bool vanish = false;
+        if (threadIdx.x == 0) s_bad = 0;
+        __syncthreads();              // reset before any thread can flag this row
+        double acc = 0.0;
+        for (int64_t qb = q0; qb < q1; qb += kTaylorThreads) {
+            // Stage this round's contributing terms.
+            const int64_t q = qb + threadIdx.x;
+            int32_t a[kMaxDegree];
+            int d = 0;
+            bool keep = false;
+            if (q < q1) {
 #pragma unroll
                 for (int i = 0; i < kMaxDegree; ++i) {
                     a[i] = i < D ? var[q * D + i] : -1;
-                    if (a[i] >= n) bad = true;
-                    if (a[i] < 0 || a[i] >= n) { a[i] = -1; pos[i] = 0; continue; }
-                    ++d;
-                    unsigned mk = 0;
-#pragma unroll
-                    for (int l = 0; l < M; ++l) mk |= unsigned(t[l] == a[i]) << l;
-                    pos[i] = mk;
-                    vanish |= mk == 0;
+                    if (a[i] >= n) s_bad = 1;
+                    if (a[i] < 0 || a[i] >= n) a[i] = -1;
+                    else ++d;
                 }
-                if (d < M) continue;
-                if (!x_eq && (d != M || vanish)) continue;
-                const double c = coef[q];
-                const int m = d - M + 1;
-                for (int e = 0; e < m; ++e) {
-                    const double s = node(e);
-                    double pe = 0.0;
-                    for (unsigned S = x_eq ? 0u : 1u; S < (1u << M); ++S) {
-                        double prod = c;
+                keep = d >= M && (x_eq || d == M);
+            }
+            const uint64_t bal = __ballot(keep);
+            if (lane == 0) s_wcnt[wave] = __popcll(bal);
+            __syncthreads();
+            int base = 0, total = 0;
 #pragma unroll
-                        for (int i = 0; i < kMaxDegree; ++i) {
-                            if (a[i] < 0) continue;
-                            const double y = double(__popc(pos[i] & S));
-                            prod *= x_eq ? fma(s, y, x_eq[a[i]]) : s * y;
-                        }
-                        pe += ((M - __popc(S)) & 1) ? -prod : prod;
+            for (int w = 0; w < NW; ++w) {
+                base += w < wave ? s_wcnt[w] : 0;
+                total += s_wcnt[w];
+            }
+            if (keep) {
+                const int slot = base + __popcll(bal & ((uint64_t(1) << lane) - 1));
+                s_coef[slot] = coef[q];
+                s_deg[slot] = d;
+                int m = 0;
+#pragma unroll
+                for (int i = 0; i < kMaxDegree; ++i)
+                    if (a[i] >= 0) s_var[slot][m++] = a[i];
+            }
+            __syncthreads();
+            if (live) {
+                for (int u = 0; u < total; ++u) {
+                    const int du = s_deg[u];
+                    // The term's variables and, per variable, the positions of t holding it
+                    // (a bit mask): y_S of that variable is popcount(mask & S).
+                    int32_t v[kMaxDegree];
+                    unsigned pos[kMaxDegree];
+                    bool vanish = false;
+#pragma unroll
+                    for (int i = 0; i < kMaxDegree; ++i) {
+                        v[i] = i < du ? s_var[u][i] : -1;
+                        unsigned mk = 0;
+#pragma unroll
+                        for (int l = 0; l < M; ++l) mk |= unsigned(t[l] == v[i]) << l;
+                        pos[i] = mk;
+                        vanish |= i < du && mk == 0;
                     }
-                    acc = fma(node_weight(e, m, M), pe, acc);
+                    if (!x_eq && vanish) continue;
+                    const double c = s_coef[u];
+                    const int m = du - M + 1;
+                    for (int e = 0; e < m; ++e) {
+                        const double sn = node(e);
+                        double pe = 0.0;
+                        for (unsigned S = x_eq ? 0u : 1u; S < (1u << M); ++S) {
+                            double prod = c;
+#pragma unroll
+                            for (int i = 0; i < kMaxDegree; ++i) {
+                                if (i >= du) continue;
+                                const double y = double(__popc(pos[i] & S));
+                                prod *= x_eq ? fma(sn, y, x_eq[v[i]]) : sn * y;
+                            }
+                            pe += ((M - __popc(S)) & 1) ? -prod : prod;
+                        }
+                        acc = fma(node_weight(e, m, M), pe, acc);
+                    }
                 }
             }
-            out[kr * UM + r] = bad ? __builtin_nan("") : acc;
+            __syncthreads();          // the staged terms are rewritten next round
         }
+        __syncthreads();              // every flag of this row is set
+        if (live) out[kr * UM + r] = s_bad ? __builtin_nan("") : acc;
+        __syncthreads();              // s_bad is read before the next row resets it
     }
 }
 
@@ -117,8 +168,11 @@ template <int M>
 hipError_t launch_taylor(int64_t n, int64_t k0, int64_t rows, int64_t UM, const npf_poly &p,
                          double *out, hipStream_t s)
 {
+    // Every rank has its thread (the workgroups stage the row's terms together); U_M < 2^40
+    // and an output that fits the device keep bx far below the grid limit.
     const int64_t bx = (UM + kTaylorThreads - 1) / kTaylorThreads;
-    const dim3 grid(unsigned(bx < (1 << 20) ? bx : (1 << 20)), unsigned(rows < 65535 ? rows : 65535));
+    if (bx > 0x7fffffff) return hipErrorInvalidConfiguration;
+    const dim3 grid(unsigned(bx), unsigned(rows < 65535 ? rows : 65535));
     hipLaunchKernelGGL(taylor_fill<M>, grid, dim3(kTaylorThreads), 0, s, n, k0, rows, UM,
                        p.eq_ptr, p.n_terms, p.coef, p.var, int(p.max_degree), p.x_eq, out);
     return hipGetLastError();
