@@ -4,8 +4,10 @@
 // M-i, rank rs).  Per (p, s) item this is a [t x a] x [a x j] complex product whose right
 // operand rows are gathered from the symmetric storage of T_{i-1}; the gather table
 // rank(sort(a U s)) is built once per item in LDS (double-buffered, one barrier per item).
-// Wave w of a workgroup owns 16 modes; every wave sweeps all t tiles of the item so each
-// gathered row is read once.  Phi stays in LDS when it fits.
+// Wave w of a workgroup owns 16 modes and sweeps NTT t tiles of the item: the t tiles are
+// dealt to grid.z in groups of NTT (at most four, so that the accumulators leave registers
+// for two waves per SIMD), and a row is gathered once per group.  Phi stays in LDS when it
+// fits.  The gathered row of the next K-step is loaded while the current one's products run.
 #include "npf_device.h"
 #include "npf_internal.h"
 #include "npf_mfma.h"
@@ -35,7 +37,7 @@ template <Eng E> constexpr int64_t phi_bytes(int64_t npad)
 }
 
 template <Eng E, int NTT, bool RES>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, 2)
 stage_mfma(StageArgs a)
 {
     using T = EngT<E>;
@@ -48,6 +50,7 @@ stage_mfma(StageArgs a)
     const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
     const bool wave_on = jw < a.Jpad;
     const int ntt = int(a.npad / 16);
+    const int tz0 = int(blockIdx.z) * NTT;          // first t tile of this group
     const int64_t N2 = a.npad * a.npad;
 
     __shared__ int32_t sidx[2][kMaxN];
@@ -74,9 +77,9 @@ stage_mfma(StageArgs a)
             sidx[parity][threadIdx.x] = int32_t(ir.rank(int32_t(threadIdx.x)));
         }
         __syncthreads();
-        if (!wave_on) continue;
-        const int32_t *idx = sidx[parity];
         const int tt0 = m / 16;
+        if (!wave_on || tz0 + NTT <= tt0) continue;        // no t >= m in this group
+        const int32_t *idx = sidx[parity];
         const cplx *src = static_cast<const cplx *>(a.in) + rp * a.U_in * a.Jpad + jw + c;
 
         acc_t sr[NTT], si[NTT];
@@ -85,15 +88,19 @@ stage_mfma(StageArgs a)
 
         if constexpr (E != Eng::BF3) {
             const cplx *Ph = reinterpret_cast<const cplx *>(phiB);
+            auto gather = [&](int64_t ar) {
+                return ar < a.n ? src[int64_t(idx[ar]) * a.Jpad] : cplx{0, 0};
+            };
+            cplx xn = gather(g);
             for (int64_t a0 = 0; a0 < a.npad; a0 += 4) {
                 const int64_t ar = a0 + g;
-                cplx x;
-                if (ar < a.n) x = src[int64_t(idx[ar]) * a.Jpad];
-                else x = cplx{0, 0};
+                const cplx x = xn;
+                if (a0 + 4 < a.npad) xn = gather(ar + 4);
 #pragma unroll
                 for (int tt = 0; tt < NTT; ++tt) {
-                    if (tt < tt0 || tt >= ntt) continue;
-                    const cplx ph = Ph[ar * a.npad + tt * 16 + c];
+                    const int tg = tz0 + tt;
+                    if (tg < tt0 || tg >= ntt) continue;
+                    const cplx ph = Ph[ar * a.npad + tg * 16 + c];
                     sr[tt] = mfma(ph.x, x.x, sr[tt]);
                     sr[tt] = mfma(real(-ph.y), x.y, sr[tt]);
                     si[tt] = mfma(ph.x, x.y, si[tt]);
@@ -117,8 +124,9 @@ stage_mfma(StageArgs a)
                 }
 #pragma unroll
                 for (int tt = 0; tt < NTT; ++tt) {
-                    if (tt < tt0 || tt >= ntt) continue;
-                    const int64_t pidx = ((a0 / 8 + g) * a.npad + tt * 16 + c) * 8;
+                    const int tg = tz0 + tt;
+                    if (tg < tt0 || tg >= ntt) continue;
+                    const int64_t pidx = ((a0 / 8 + g) * a.npad + tg * 16 + c) * 8;
                     Split3 pr, pi;
                     pr.h = *reinterpret_cast<const v8bf *>(Ph + 0 * N2 + pidx);
                     pr.m = *reinterpret_cast<const v8bf *>(Ph + 1 * N2 + pidx);
@@ -138,10 +146,11 @@ stage_mfma(StageArgs a)
         cplx *dst = static_cast<cplx *>(a.out) + rs * a.Jpad + jw + c;
 #pragma unroll
         for (int tt = 0; tt < NTT; ++tt) {
-            if (tt < tt0 || tt >= ntt) continue;
+            const int tg = tz0 + tt;
+            if (tg < tt0 || tg >= ntt) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t t = int64_t(tt) * 16 + out_row<E>(r, g);
+                const int64_t t = int64_t(tg) * 16 + out_row<E>(r, g);
                 if (t < m || t >= a.n) continue;
                 const int64_t row = rp + colex_term_c(t, a.i);
                 dst[row * a.U_suf * a.Jpad] = cplx{real(sr[tt][r]), real(si[tt][r])};
@@ -166,28 +175,25 @@ void launch_one(const dim3 &grid, const StageArgs &sa, hipStream_t s)
 }
 
 template <Eng E>
-hipError_t launch_stage_eng(const StageArgs &sa, int ntt, int64_t groups, int64_t jgroups,
-                            hipStream_t s)
+hipError_t launch_stage_eng(const StageArgs &sa, int ntt, int64_t jgroups, hipStream_t s)
 {
-    const dim3 grid{unsigned(groups), unsigned(jgroups), 1u};
+    // t tiles per workgroup: all of them up to four, else groups of four over grid.z.
+    const int tg = ntt <= 4 ? ntt : 4;
+    const int64_t zg = (ntt + tg - 1) / tg;
+    int64_t groups = 1024 / (jgroups * zg);
+    if (groups > sa.items) groups = sa.items;
+    if (groups < 1) groups = 1;
+    const dim3 grid{unsigned(groups), unsigned(jgroups), unsigned(zg)};
     const bool res = phi_bytes<E>(sa.npad) <= kResidentBytes;
-#define NPF_STAGE_CASE(K)                                                   \
-    case K:                                                                 \
-        if (res) launch_one<E, K, true>(grid, sa, s);                       \
-        else launch_one<E, K, false>(grid, sa, s);                          \
-        break;
-    switch (ntt) {
-        NPF_STAGE_CASE(2)
-        NPF_STAGE_CASE(4)
-        NPF_STAGE_CASE(6)
-        NPF_STAGE_CASE(8)
-        NPF_STAGE_CASE(10)
-        NPF_STAGE_CASE(12)
-        NPF_STAGE_CASE(14)
-        NPF_STAGE_CASE(16)
-    default: return hipErrorInvalidValue;
+    if (tg == 2) {
+        if (res) launch_one<E, 2, true>(grid, sa, s);
+        else launch_one<E, 2, false>(grid, sa, s);
+    } else if (tg == 4) {
+        if (res) launch_one<E, 4, true>(grid, sa, s);
+        else launch_one<E, 4, false>(grid, sa, s);
+    } else {
+        return hipErrorInvalidValue;
     }
-#undef NPF_STAGE_CASE
     return hipGetLastError();
 }
 
@@ -217,13 +223,10 @@ hipError_t launch_stage_mfma(const ChainArgs &ca, int i)
     sa.i = i;
     const int ntt = int(p.npad / 16);
     const int64_t jgroups = (p.Jpad + 63) / 64;
-    int64_t groups = 1024 / jgroups;
-    if (groups > sa.items) groups = sa.items;
-    if (groups < 1) groups = 1;
     switch (p.prec) {
-    case NPF_FP64: return launch_stage_eng<Eng::F64>(sa, ntt, groups, jgroups, ca.stream);
-    case NPF_FP32: return launch_stage_eng<Eng::F32>(sa, ntt, groups, jgroups, ca.stream);
-    default: return launch_stage_eng<Eng::BF3>(sa, ntt, groups, jgroups, ca.stream);
+    case NPF_FP64: return launch_stage_eng<Eng::F64>(sa, ntt, jgroups, ca.stream);
+    case NPF_FP32: return launch_stage_eng<Eng::F32>(sa, ntt, jgroups, ca.stream);
+    default: return launch_stage_eng<Eng::BF3>(sa, ntt, jgroups, ca.stream);
     }
 }
 
