@@ -133,6 +133,10 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
                     const Split3 xng = negx3(xi);
 #pragma unroll
                     for (int u = U0; u < 2; ++u) {
+                        // A tile of padding rows only (not at 160 states, where the test
+                        // costs spills).
+                        if constexpr (NP != 160)
+                            if (t_base + 16 * u >= nn) continue;
                         const int pidx = ((kc * 4 + g) * 32 + 16 * u + c) * 8;
                         Split3 pr, pi;
                         pr.h = *reinterpret_cast<const v8bf *>(Lp + 0 * PLP + pidx);

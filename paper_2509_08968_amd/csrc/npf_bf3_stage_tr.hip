@@ -380,6 +380,7 @@ stage_bf3_sl(Bf3Args a)
                     const Split3 xng = negx3(xi);
 #pragma unroll
                     for (int tt = T0; tt < TT; ++tt) {
+                        if (t_base + tt * 16 >= nn) continue;   // a tile of padding rows only
                         const int pidx = ((kc * 4 + g) * TW + tt * 16 + c) * 8;
                         Split3 pr, pi;
                         pr.h = *reinterpret_cast<const v8bf *>(Lphi + 0 * PL + pidx);
