@@ -231,7 +231,7 @@ fused_last(FusedArgs a)
 #pragma unroll
         for (int kt = 0; kt < NKTW; ++kt) rr[kt] = ri[kt] = acc_t{0, 0, 0, 0};
 
-        for (int64_t t0 = (m / TC) * TC; t0 < a.npad; t0 += TC) {
+        for (int64_t t0 = (m / TC) * TC; t0 < a.n; t0 += TC) {     // chunks holding some t < n
             // ---------------- GEMM1: S^T[t][j] over a, tiles of 16 t.
             constexpr int NT1 = (E == Eng::BF3) ? 2 : 1;
             acc_t sr[NT1], si[NT1];

@@ -49,7 +49,7 @@ stage_mfma(StageArgs a)
     const int g = lane >> 4, c = lane & 15;
     const int64_t jw = int64_t(blockIdx.y) * 64 + wave * 16;
     const bool wave_on = jw < a.Jpad;
-    const int ntt = int(a.npad / 16);
+    const int ntt = int((a.n + 15) / 16);           // t tiles holding some t < n
     const int tz0 = int(blockIdx.z) * NTT;          // first t tile of this group
     const int64_t N2 = a.npad * a.npad;
 
@@ -177,8 +177,9 @@ void launch_one(const dim3 &grid, const StageArgs &sa, hipStream_t s)
 template <Eng E>
 hipError_t launch_stage_eng(const StageArgs &sa, int ntt, int64_t jgroups, hipStream_t s)
 {
-    // t tiles per workgroup: all of them up to four, else groups of four over grid.z.
-    const int tg = ntt <= 4 ? ntt : 4;
+    // t tiles per workgroup: two or four (tiles past the last one holding some t < n are
+    // skipped), more in groups of four over grid.z.
+    const int tg = ntt <= 2 ? 2 : 4;
     const int64_t zg = (ntt + tg - 1) / tg;
     int64_t groups = 1024 / (jgroups * zg);
     if (groups > sa.items) groups = sa.items;
@@ -221,7 +222,7 @@ hipError_t launch_stage_mfma(const ChainArgs &ca, int i)
     sa.items = p.U[i - 1] * p.U[M - i];
     sa.M = M;
     sa.i = i;
-    const int ntt = int(p.npad / 16);
+    const int ntt = int((p.n + 15) / 16);
     const int64_t jgroups = (p.Jpad + 63) / 64;
     switch (p.prec) {
     case NPF_FP64: return launch_stage_eng<Eng::F64>(sa, ntt, jgroups, ca.stream);
