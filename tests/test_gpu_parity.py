@@ -54,6 +54,36 @@ def test_staged_steps_fp64(torch_dev, case):
         check(P.cpu().numpy(), ref[M]["P"], TOL["fp64"], "P")
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["n12-o3-dense", "n9-o4-dense-odd", "n24-o3-blocksparse",
+                                  "n72-o3-dense", "n130-o2-dense"])
+def test_staged_steps_mixed(torch_dev, case, precision):
+    """The staged entry points on the mixed paths (chain in FP32 or split-BF16, C written in
+    FP64; divisor, division and reduction in FP64): C, h and P against the oracle."""
+    torch, dev = torch_dev
+    s = PARITY_CASES[case]()
+    print(f"[staged {precision}] {case}", flush=True)
+    ref, _ = _oracle_all(s)
+    d = B.upload_system(s, dev)
+    plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta,
+                  support_max=s.support_max)
+    ws = plan.workspace(dev)
+    for M in s.orders:
+        UM = plan.unique_tuples[M]
+        C = torch.empty((s.n, UM), dtype=torch.complex128, device=dev)
+        plan.modal_contract(M, B.NPF_ALL_BLOCKS, d.tensors[M - 2], d.U, d.V, ws, C)
+        torch.cuda.synchronize()
+        check(C.cpu().numpy(), ref[M]["C"], TOL[precision], f"C_{M}")
+        plan.normal_form(M, B.NPF_ALL_BLOCKS, d.lam, C)
+        torch.cuda.synchronize()
+        check(C.cpu().numpy(), ref[M]["h"], TOL[precision], f"h_{M}")
+        P = torch.zeros((s.n, s.n), dtype=torch.complex128, device=dev)
+        plan.assemble(M, B.NPF_ALL_BLOCKS, C, d.U, P)
+        torch.cuda.synchronize()
+        check(P.cpu().numpy(), ref[M]["P"], TOL[precision], f"P_{M}")
+    plan.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("case", sorted(PARITY_CASES))
 def test_run_matches_oracle(torch_dev, case, precision):
