@@ -54,7 +54,8 @@ extern "C" {
 
 /* Arithmetic of the contractions (the divisor and the NPF accumulation are always FP64). */
 #define NPF_FP64 0          /* FP64 operands, FP64 accumulation                    */
-#define NPF_FP32 1          /* FP32 operands, FP32 accumulation per tile           */
+#define NPF_FP32 1          /* FP32 operands and intermediates, exact products
+                               accumulated in FP64                               */
 #define NPF_BF16X3 2        /* FP32 values split in three BF16 terms, six products
                                per multiply, FP32 accumulation per tile            */
 /* NPF_FP32 and NPF_BF16X3 serve order_max <= 4 (npf_plan_create returns NPF_E_UNSUPPORTED
@@ -85,7 +86,7 @@ typedef struct npf_tensor {
 
 /* Problem description (host memory; copied by npf_plan_create). */
 typedef struct npf_problem {
-    int64_t n;                 /* states = modes, n >= 1                              */
+    int64_t n;                 /* states = modes, 1 <= n <= 512 (NPF_BF16X3: 256)     */
     int32_t order_max;         /* N, 2 <= N <= NPF_MAX_ORDER                          */
     int32_t precision;         /* NPF_FP64 / NPF_FP32 / NPF_BF16X3                    */
     double eps;                /* divisor clamp of Alg. 2 step 9, > 0                 */

@@ -72,7 +72,7 @@ __device__ __forceinline__ void fused_bf3_body(const Bf3Args &a, const BlockPos 
         pkn = (itn < a.items) ? a.ptab[itn] : 0;
         int32_t p[M - 1];
 #pragma unroll
-        for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
+        for (int q = 0; q < M - 1; ++q) p[q] = tuple_at(pk, q);
         double2 lam_p = Llam[p[0]];
         double den = 1.0;
         int run = 1;

@@ -89,7 +89,7 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
 #pragma unroll
         for (int s = 0; s < 8; ++s) dst[s] = Xp[min(o0 + s * jp, rowlim)];
     };
-    auto last_of = [&](uint64_t pk) { return int((pk >> (8 * (M - 2))) & 0xff); };
+    auto last_of = [&](uint64_t pk) { return int(tuple_at(pk, M - 2)); };
     auto active = [&](uint64_t pk) { return t_base + 32 > last_of(pk); };
 
     // The item loop is uniform over the workgroup (it holds two barriers).
@@ -193,7 +193,7 @@ __device__ __forceinline__ void fused_bf3_tr_body(const Bf3Args &a, const BlockP
         if (on) {
             int32_t p[M - 1];
 #pragma unroll
-            for (int q = 0; q < M - 1; ++q) p[q] = int32_t((pk >> (8 * q)) & 0xff);
+            for (int q = 0; q < M - 1; ++q) p[q] = tuple_at(pk, q);
             double2 lam_p = Llam[p[0]];
             double den = 1.0;
             int run = 1;

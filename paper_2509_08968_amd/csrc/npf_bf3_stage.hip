@@ -36,7 +36,7 @@ __device__ __forceinline__ void stage_bf3_body(const Bf3Args &a, const BlockPos 
             int qq = 0;
 #pragma unroll
             for (int l = 0; l < SUF; ++l) {
-                const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
+                const int32_t sl = tuple_at(pk, l);
                 if (sl <= x) {
                     r += colex_term_c(sl, l + 1);
                     ++qq;
@@ -91,7 +91,7 @@ __device__ __forceinline__ void stage_bf3_body(const Bf3Args &a, const BlockPos 
 
         const int64_t rp = it / a.U_suf, rs = it % a.U_suf;
         int m = 0;
-        if (a.i > 1) m = int((a.ptab[rp] >> (8 * (a.i - 2))) & 0xff);
+        if (a.i > 1) m = int(tuple_at(a.ptab[rp], a.i - 2));
         const int tt0 = m / 16;
 
         v4f sr[NTT], si[NTT], srl[NTT], sil[NTT];

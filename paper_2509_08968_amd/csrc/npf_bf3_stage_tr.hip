@@ -81,7 +81,7 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
             if (x == 0) {
                 sbase[buf][q][0] = rp * a.U_in * a.Jpad;
                 sbase[buf][q][1] = (rp * a.U_suf + rs) * a.Jpad;
-                sm[buf][q] = (a.i > 1) ? int((a.ptab[rp] >> (8 * (a.i - 2))) & 0xff) : 0;
+                sm[buf][q] = (a.i > 1) ? int(tuple_at(a.ptab[rp], a.i - 2)) : 0;
             }
             const uint64_t pk = a.stab[rs];
             const int32_t xe = (x < nn) ? x : 0;
@@ -89,7 +89,7 @@ __device__ __forceinline__ void stage_bf3_tr_body(const Bf3Args &a, const BlockP
             int qq = 0;
 #pragma unroll
             for (int l = 0; l < SUF; ++l) {
-                const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
+                const int32_t sl = tuple_at(pk, l);
                 if (sl <= xe) {
                     r += colex_term_c(sl, l + 1);
                     ++qq;
@@ -264,7 +264,7 @@ stage_bf3_sl(Bf3Args a)
             if (x == 0) {
                 sbase[buf][q][0] = rp * a.U_in * a.Jpad;
                 sbase[buf][q][1] = (rp * a.U_suf + rs) * a.Jpad;
-                sm[buf][q] = (a.i > 1) ? int((a.ptab[rp] >> (8 * (a.i - 2))) & 0xff) : 0;
+                sm[buf][q] = (a.i > 1) ? int(tuple_at(a.ptab[rp], a.i - 2)) : 0;
             }
             const uint64_t pk = a.stab[rs];
             const int32_t xe = (x < nn) ? x : 0;
@@ -272,7 +272,7 @@ stage_bf3_sl(Bf3Args a)
             int qq = 0;
 #pragma unroll
             for (int l = 0; l < SUF; ++l) {
-                const int32_t sl = int32_t((pk >> (8 * l)) & 0xff);
+                const int32_t sl = tuple_at(pk, l);
                 if (sl <= xe) {
                     r += colex_term_c(sl, l + 1);
                     ++qq;

@@ -51,10 +51,24 @@ __host__ __device__ __forceinline__ double hash_entry(uint64_t seed, double scal
     return y * scale;
 }
 
-// Sorted tuples of length <= 7 over n <= 256 states are packed 8 bits per entry.
+// Sorted tuples of length <= 7 over n <= 512 states are packed 9 bits per entry, entry i in
+// bits [9i, 9i + 9).
+constexpr int kTupleBits = 9;
+constexpr uint64_t kTupleMask = (uint64_t(1) << kTupleBits) - 1;
+
+__host__ __device__ __forceinline__ int32_t tuple_at(uint64_t pk, int i)
+{
+    return int32_t((pk >> (kTupleBits * i)) & kTupleMask);
+}
+
+__host__ __device__ __forceinline__ uint64_t tuple_entry(int32_t v, int i)
+{
+    return uint64_t(v) << (kTupleBits * i);
+}
+
 __host__ __device__ __forceinline__ void unpack_tuple(uint64_t pk, int m, int32_t *t)
 {
-    for (int i = 0; i < m; ++i) t[i] = int32_t((pk >> (8 * i)) & 0xff);
+    for (int i = 0; i < m; ++i) t[i] = tuple_at(pk, i);
 }
 
 // Colex rank of a sorted m-tuple.
@@ -160,7 +174,7 @@ __host__ __device__ __forceinline__ void unpack_tuple_reg(uint64_t pk, int m,
                                                           int32_t (&t)[NPF_MAX_ORDER])
 {
 #pragma unroll
-    for (int i = 0; i < NPF_MAX_ORDER; ++i) t[i] = (i < m) ? int32_t((pk >> (8 * i)) & 0xff) : 0;
+    for (int i = 0; i < NPF_MAX_ORDER; ++i) t[i] = (i < m) ? tuple_at(pk, i) : 0;
 }
 
 // Orderings of a sorted tuple: M! / prod(count_v!).

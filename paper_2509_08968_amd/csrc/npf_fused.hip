@@ -63,7 +63,7 @@ prepare(const double2 *__restrict__ Phi, const double2 *__restrict__ Psi, double
             int32_t t[NPF_MAX_ORDER];
             colex_unrank(y, m, n, t);
             uint64_t pk = 0;
-            for (int i = 0; i < m; ++i) pk |= uint64_t(t[i]) << (8 * i);
+            for (int i = 0; i < m; ++i) pk |= tuple_entry(t[i], i);
             ttab[tt.off[m] + y] = pk;
             continue;
         }

@@ -62,8 +62,8 @@ struct Layout {
     int64_t total = 0;
 };
 
-// Largest number of output modes of one call (n <= 256 for the MFMA kernels).
-constexpr int kMaxModes = 256;
+// Largest number of output modes of one call (n <= 512).
+constexpr int kMaxModes = 512;
 constexpr uint16_t kNoRow = 0xFFFF;
 
 // Output rows of the computed modes c0 .. c0 + J - 1 (passed by value to the kernels that

@@ -258,7 +258,9 @@ extern "C" int npf_plan_create(const npf_problem *problem, npf_plan_t *plan_out)
         return fail(NPF_E_INVALID, "unknown derivative-tensor convention");
     if (!(q.check_tol >= 0.0) || !std::isfinite(q.check_tol))
         return fail(NPF_E_INVALID, "check_tol must be >= 0");
-    if (q.n > 256) return fail(NPF_E_UNSUPPORTED, "n > 256 is not supported by the MFMA kernels");
+    if (q.n > 512) return fail(NPF_E_UNSUPPORTED, "n > 512 is not supported (tuple entries are 9 bits)");
+    if (q.n > 256 && q.precision == NPF_BF16X3)
+        return fail(NPF_E_UNSUPPORTED, "split-BF16 plans serve n <= 256; use FP32 or FP64 above");
     // The mixed paths store C once per sorted tuple in FP32, and every ordering of the tuple
     // reuses that one rounding; beyond order 4 (m(t) up to 120 orderings) the coherent error
     // exceeds the 1e-6 bound of these paths, so orders 5 and 6 are served in FP64 only.

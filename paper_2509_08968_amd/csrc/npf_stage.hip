@@ -18,7 +18,7 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kMaxN = 256;          // states supported by the MFMA kernels
+constexpr int kMaxN = 512;          // states supported by the MFMA kernels
 constexpr int64_t kResidentBytes = 128 * 1024;
 
 struct StageArgs {
@@ -71,10 +71,11 @@ stage_mfma(StageArgs a)
         if (a.i > 1) unpack_tuple(a.ptab[rp], a.i - 1, p);
         if (sufl > 0) unpack_tuple(a.stab[rs], sufl, s);
         const int m = (a.i > 1) ? p[a.i - 2] : 0;
-        if (threadIdx.x < a.n) {
+        {
             InsertRank ir;
             ir.init(s, sufl);
-            sidx[parity][threadIdx.x] = int32_t(ir.rank(int32_t(threadIdx.x)));
+            for (int x = threadIdx.x; x < a.n; x += blockDim.x)
+                sidx[parity][x] = int32_t(ir.rank(int32_t(x)));
         }
         __syncthreads();
         const int tt0 = m / 16;

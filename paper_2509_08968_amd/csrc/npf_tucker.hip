@@ -203,7 +203,7 @@ tucker_w3(const uint64_t *__restrict__ ptab, int64_t np, const double2 *__restri
          rp += int64_t(gridDim.x) * TPB) {
         if (q >= smax) continue;
         const uint64_t pk = ptab[rp];
-        const int p0 = int(pk & 0xff), p1 = int((pk >> 8) & 0xff);
+        const int p0 = tuple_at(pk, 0), p1 = tuple_at(pk, 1);
         double2 y[kTuckerMaxSupport];
 #pragma unroll
         for (int b0 = 0; b0 < kTuckerMaxSupport; ++b0)     // independent loads, issued together

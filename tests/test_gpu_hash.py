@@ -72,6 +72,10 @@ LARGE_CASES = {
     "n200-o3-hash-J16": (lambda: I.hash_system(200, [2, 3], 4603), 16, ["bf16x3"]),
     "n250-o3-dense": (lambda: I.dense_system(250, [2, 3], 4604), 0, ["bf16x3"]),
     "n100-o4-hash-J48": (lambda: I.hash_system(100, [2, 3, 4], 4605), 48, ["bf16x3"]),
+    # above 256 states: the FP32 and FP64 paths (tuple entries of 9 bits), NPCC-sized n = 351
+    "n300-o3-hash": (lambda: I.hash_system(300, [2, 3], 4606), 0, ["fp64", "fp32"]),
+    "n351-o3-hash": (lambda: I.hash_system(351, [2, 3], 4607), 0, ["fp64"]),
+    "n300-o2-dense": (lambda: I.dense_system(300, [2], 4608), 0, ["fp64"]),
 }
 LARGE_PARAMS = [(c, p) for c, (_, _, ps) in sorted(LARGE_CASES.items()) for p in ps]
 

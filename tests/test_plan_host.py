@@ -70,7 +70,8 @@ def test_plan_counts_and_entries():
     (dict(n=8, order_max=2, tau=-1.0), B.NPF_E_INVALID),
     (dict(n=8, order_max=2, budget_bytes=-5), B.NPF_E_INVALID),
     (dict(n=128, order_max=4, budget_bytes=1 << 20), B.NPF_E_BUDGET),
-    (dict(n=257, order_max=2), B.NPF_E_UNSUPPORTED),
+    (dict(n=513, order_max=2), B.NPF_E_UNSUPPORTED),
+    (dict(n=257, order_max=2, precision="bf16x3"), B.NPF_E_UNSUPPORTED),
 ])
 def test_plan_rejects(kw, code):
     with pytest.raises(B.NpfError) as e:
@@ -97,6 +98,12 @@ def test_plan_accepts_the_largest_size():
     assert p.unique_tuples[4] == 259 * 258 * 257 * 256 // 24
     assert p.block_modes * p.n_blocks >= 256
     p.close()
+    # FP32 and FP64 plans go to 512 states (tuple entries of 9 bits)
+    for prec in ("fp32", "fp64"):
+        p = B.Plan(512, 3, prec, budget_bytes=64 << 30)
+        assert p.unique_tuples[3] == 514 * 513 * 512 // 6
+        assert p.block_modes * p.n_blocks >= 512
+        p.close()
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
