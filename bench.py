@@ -47,6 +47,11 @@ WORKLOAD_BUDGET = {"n128-o4-dense-resonant": {"*": 64 << 30},
                    "n200-o4-dense-hash": {"*": 176 << 30, "fp64": 192 << 30}}
 
 
+# Budget of the generated-versus-stored pair: the stored order-4 tensor of 200 states takes
+# 110 GB beside the workspace, so both legs run under 140 GB (blocks of 16 modes).
+SOURCE_PAIR_BUDGET = 140 << 30
+
+
 def budget_for(workload, precision):
     b = WORKLOAD_BUDGET.get(workload, {})
     return b.get(precision, b.get("*", 0))
@@ -512,6 +517,44 @@ def interaction_leg(s, sysm, precision, budget, conj, device, refP, modes):
     return out
 
 
+def source_pair(s, sysm, precision, conj, device, budget, errors):
+    """The workload with its hash-generated tensors generated inside the upper-index
+    contraction (as benchmarked) and stored in HBM (materialised once with npf_hash_fill,
+    outside the timed region, and read as dense tensors), both under the same budget so
+    that the stored tensors fit beside the workspace: one warm step and one timed step each."""
+    import torch
+    from paper_2509_08968_amd import binding as B
+    if not s.hashed:
+        return None
+    stored, bufs = [], []
+    for t in sysm.tensors:
+        if t.kind != B.SRC_HASH:
+            stored.append(t)
+            continue
+        M = t.order
+        UM = math.comb(s.n + M - 1, M)
+        buf = torch.empty(s.n * UM, dtype=torch.float64, device=device)
+        B.hash_fill(s.n, M, t.desc.seed, t.desc.scale, 0, s.n, buf)
+        bufs.append(buf)
+        stored.append(B.DeviceTensor(M, B.SRC_DENSE, {"values": buf},
+                                     B.NpfTensor(B.SRC_DENSE, M, buf.data_ptr(), None, None, None,
+                                                 0, 0)))
+    torch.cuda.synchronize()
+    out = {"budget_bytes": budget, "stored_tensor_bytes": sum(8 * b.numel() for b in bufs)}
+    for name, tens in (("generated", sysm.tensors), ("stored", stored)):
+        dev = B.DeviceSystem(sysm.n, sysm.lam, sysm.U, sysm.V, tens, sysm.orders, sysm.support_max)
+        r = time_path(dev, s, precision, 1, 1, device, 0, budget, s.n > 128, conj)
+        out[name] = {"ms_per_step": r["ms_per_step"], "value": r["plan"].modal_entries / (r["ms_per_step"] * 1e-3),
+                     "rel_err": errors(r), "block_modes": r["plan"].block_modes,
+                     "blocks": r["plan"].n_blocks}
+        r["plan"].close()
+        del r
+        torch.cuda.empty_cache()
+    del bufs, stored
+    torch.cuda.empty_cache()
+    return out
+
+
 def taylor_leg(device, n=200):
     """npf_taylor_fill (the numerical Taylor expansion of Alg. 1 on the device) for a seeded
     polynomial field of n states with terms of degrees 1-4 about a nonzero x*: all rows of
@@ -582,6 +625,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-source-pair", action="store_true",
+                    help="skip the generated-versus-stored tensor pair (hash workloads)")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the interaction-factor and derivative-tensor legs")
     ap.add_argument("--profile-steps", type=int, default=2,
@@ -672,6 +717,13 @@ def main():
     legs = {p: leg(p) for p in ("fp32", "fp64")
             if p != args.precision and not getattr(args, f"no_{p}")}
 
+    pair = None
+    if s.hashed and not args.no_source_pair:
+        torch.cuda.empty_cache()
+        pair = source_pair(s, sysm, args.precision, conj, device, SOURCE_PAIR_BUDGET, errors)
+        log(f"[bench] generated vs stored tensors: "
+            f"{pair['generated']['ms_per_step']:.1f} / {pair['stored']['ms_per_step']:.1f} ms")
+
     inter = taylor = None
     if not args.no_next:
         torch.cuda.empty_cache()
@@ -696,11 +748,14 @@ def main():
         roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
                 "frac": achieved / peak,
                 "traffic": measured_traffic(args.workload, args.precision, name),
+                "traffic_GBps": None,
                 "algorithmic_bytes": byts, "algorithmic_flops": flops, "kernel": name,
                 "avg_launch_ms": tot / cnt, "launches_per_step": cnt / psteps,
                 "share_of_step": tot / psteps / res["ms_per_step"],
                 "timing": f"HIP events around every launch on its stream, {psteps} eager "
                           "steps after the timed ones"}
+        if roof["traffic"]:
+            roof["traffic_GBps"] = roof["traffic"] / avg_s / 1e9
         if mfma:
             roof["executed_mfma_frac"] = achieved * SPLIT_PRODUCTS[args.precision] / peak
         log(f"[bench] kernels: " + ", ".join(f"{k}={v[1] / psteps:.3f}ms"
@@ -725,6 +780,7 @@ def main():
         "rel_err_vs_oracle": err,
         "fp64_gpu": legs.get("fp64"),
         "fp32_gpu": legs.get("fp32"),
+        "tensor_source_pair": pair,
         "interaction_factors": inter,
         "derivative_tensors": taylor,
         "roofline": roof,
