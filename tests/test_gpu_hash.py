@@ -117,3 +117,40 @@ def test_workload_n200_o4_hash_sampled(torch_dev, precision):
     for M in s.orders:
         check(Ps[M][modes], cplx(g["P"][str(M)]), TOL[precision], f"P_{M}")
     check(npf[:, modes].T, cplx(g["npf_columns"]), TOL[precision], "NPF")
+
+
+CH_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hash200_ch.json")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["bf16x3", "fp32", "fp64"])
+def test_workload_n200_o4_hash_c_and_h_sampled(torch_dev, precision):
+    """C and h (Alg. 2 steps 1-11) of the n=200, orders 2-4 workload at full size, through a
+    plan that selects four output modes and the staged entry points, on 1024 sampled sorted
+    tuples per mode and order against stored oracle values (hash200_ch.json, written by
+    make_hash200_ch_golden.py, which calls only the oracle)."""
+    torch, dev = torch_dev
+    g = json.load(open(CH_GOLDEN))
+    s = I.workload_hash200()
+    modes = g["modes"]
+    d = B.upload_system(s, dev)
+    plan = B.Plan(s.n, s.order_max, precision, s.eps, s.tau, s.delta, modes=modes)
+    computed, _ = plan.modes()
+    rows = [modes.index(m) for m in computed]        # golden row of each computed mode
+    ws = plan.workspace(dev)
+    cplx = lambda a: np.asarray(a)[..., 0] + 1j * np.asarray(a)[..., 1]
+    print(f"[n200 C/h {precision}] modes {computed}", flush=True)
+    for M in s.orders:
+        e = g["orders"][str(M)]
+        ranks = torch.tensor(e["ranks"], dtype=torch.int64, device=dev)
+        C = torch.empty((len(computed), plan.unique_tuples[M]), dtype=torch.complex128, device=dev)
+        plan.modal_contract(M, B.NPF_ALL_BLOCKS, d.tensors[M - 2], d.U, d.V, ws, C)
+        torch.cuda.synchronize()
+        Cs = C[:, ranks].cpu().numpy()
+        plan.normal_form(M, B.NPF_ALL_BLOCKS, d.lam, C)
+        torch.cuda.synchronize()
+        hs = C[:, ranks].cpu().numpy()
+        del C
+        check(Cs, cplx(e["C"])[rows], TOL[precision], f"C_{M}")
+        check(hs, cplx(e["h"])[rows], TOL[precision], f"h_{M}")
+    plan.close()
