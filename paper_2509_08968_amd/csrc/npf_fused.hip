@@ -26,7 +26,7 @@ constexpr int64_t kResidentBytes = 128 * 1024;   // LDS budget for resident oper
 //   F64: phi[a][t], zeta[t][k] as double2;  F32: the same as float2;
 //   BF3: phi as 6 BF16 planes (re h/m/l, im h/m/l) in layout [pl][a/8][t][a%8],
 //        zeta as 6 planes (re h/m/l, im h/m/l) in the fragment order of zeta_frag_index.
-// Also the tables of sorted tuples of length 1..N-1 (8 bits per entry), in colex order.
+// Also the tables of sorted tuples of length 1..N-1 (9 bits per entry), in colex order.
 // With selected modes, also the Psi rows and (when lam is given) the eigenvalues of the
 // computed modes: msel[c*n + k] = Psi[row[c], k] and msel[nc*n + c] = lam[row[c]].
 // With zadd (the sum over orders of P_M, [mode][state]) the reduction's factor becomes the

@@ -24,7 +24,7 @@ int check_tensor(const npf_plan_s *p, const npf_tensor *A, int M);
 // binom(a, b) on the host (exact; 0 outside 0 <= b <= a).
 int64_t binom(int64_t a, int64_t b);
 
-// Tables of sorted tuples of length 1..maxlen (packed 8 bits per entry), in colex order:
+// Tables of sorted tuples of length 1..maxlen (packed 9 bits per entry), in colex order:
 // the tuple of rank r and length m is entry off[m] + r.
 struct TupleTables {
     int64_t count[NPF_MAX_ORDER + 1] = {0};
@@ -275,7 +275,7 @@ bool bf3_stage_supported(const npf_plan_s *p);
 // MFMA upper-index contraction for dense tensors.
 bool psi_a_mfma_supported(const npf_plan_s *p);
 hipError_t launch_psi_a_mfma(const ChainArgs &a);
-// MFMA version of one chain stage (n <= 256).
+// MFMA version of one chain stage (n <= 512).
 bool stage_mfma_supported(const npf_plan_s *p);
 hipError_t launch_stage_mfma(const ChainArgs &a, int i);
 // The launch sequence of npf_run, eagerly (no graph, orders in sequence), on workspace ws

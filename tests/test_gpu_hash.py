@@ -1,13 +1,14 @@
-"""Hash-generated derivative tensors and the kernel shapes for 65 to 256 states, on the GPU
+"""Hash-generated derivative tensors and the kernel shapes above 64 states, on the GPU
 through the C ABI.
 
 - npf_hash_fill reproduces the generator's definition bit for bit;
 - a hash-generated tensor gives bitwise the same NPFs as the same tensor stored;
 - systems of 100 to 250 states, with output-mode blocks of 16 and 32 modes (several items
   per workgroup) and with the reduction's states split over workgroups (n > 128), match
-  the oracle on sampled modes (P rows and NPF columns);
+  the oracle on sampled modes (P rows and NPF columns); so do systems of 300 and 351 states
+  on the FP32 and FP64 paths;
 - the n=200, orders 2-4 hash-generated workload at full size matches the stored oracle
-  values of its sampled modes.
+  values of its sampled modes (P rows, NPF columns, and C and h on sampled tuples).
 """
 import json
 import math
