@@ -100,9 +100,12 @@ def measured_traffic(workload, precision, kernel):
 
 
 def kernel_work(name, sysm, plan):
-    """(algorithmic flops, algorithmic HBM bytes, bound, uses MFMA) of ONE launch of a
-    kernel, from the shapes (a complex multiply-add counts 8 flops, real x complex 4)."""
-    n, J, U = sysm.n, plan.block_modes, plan.unique_tuples
+    """(algorithmic flops, algorithmic HBM bytes, bound, uses MFMA) of one launch of a
+    kernel, averaged over the plan's blocks, from the shapes (a complex multiply-add counts
+    8 flops, real x complex 4).  J is the mean number of computed modes per block: a narrow
+    last block (or padding to 16 modes) is not algorithmic work."""
+    n, U = sysm.n, plan.unique_tuples
+    J = plan.computed_modes / max(1, plan.n_blocks)
     if name == "finalize":
         return 8.0 * n * n, 16.0 * 4 * n * n, "hbm", False
     M = int(name[1])
